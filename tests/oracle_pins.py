@@ -1,0 +1,482 @@
+"""Pins that tie the CPU oracle to facts fixed outside it.
+
+Every check takes the ctypes handle of an oracle build, so the same checks run
+against the real oracle (tests/test_oracle_pins.py) and against deliberately
+broken copies of it (tests/test_oracle_mutants.py), which must each fail at
+least one of them.
+
+What pins what (all CPU, no GPU):
+  * exact rational brute force on tiny dgemm shapes, all trans cases, ld
+    padding with NaN sentinels (integer data: the exact result is a binary64
+    number, so the oracle must return it bit for bit);
+  * dgemm closed forms: identity, permutation, all-ones, single non-zero;
+  * the transposition rule (A B)^T = B^T A^T (paper Sec. 2.2, variant 'D', TT);
+  * SciPy/OpenBLAS dgemm and LAPACK dpotrf as independent libraries;
+  * dpotrf: the info closed form, exact integer factors, identity/diagonal,
+    the Pascal and 3x3 textbook fixtures, the 1x1/2x2 closed forms, the
+    reconstruction residual, untouched upper triangle;
+  * Cholesky adjoint: log-det closed form (Abar = A^-1), n = 1, central finite
+    differences.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TRANS = ("N", "T")
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _colmajor_padded(g, rows, cols, pad, integer=True, lo=-4, hi=4):
+    ld = max(1, rows + pad)
+    X = np.full((ld, max(cols, 1)), np.nan, order="F")
+    if integer:
+        X[:rows, :cols] = g.integers(lo, hi + 1, size=(rows, cols))
+    else:
+        X[:rows, :cols] = g.uniform(-1, 1, size=(rows, cols))
+    return X, ld
+
+
+def _op(X, t, rows, cols):
+    """Rows x cols matrix op(X) as a Python list of lists (exact values)."""
+    if t == "N":
+        return [[X[i, j] for j in range(cols)] for i in range(rows)]
+    return [[X[j, i] for j in range(cols)] for i in range(rows)]
+
+
+def _load_pair(name):
+    rows, mats, cur = [], [], []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("#"):
+                if cur:
+                    mats.append(np.array(cur, dtype=np.float64))
+                    cur = []
+                continue
+            if line:
+                cur.append([float(v) for v in line.split()])
+    if cur:
+        mats.append(np.array(cur, dtype=np.float64))
+    return mats[0], mats[1]
+
+
+# ----------------------------------------------------------------------------
+# dgemm
+# ----------------------------------------------------------------------------
+
+def pin_dgemm_exact_bruteforce(lib, sizes=range(0, 6), pads=(0, 3), seed=11):
+    """Exhaustive m, n, k in 0..5, four trans cases, ld padding 0 and 3.
+
+    Integer entries in [-4, 4], alpha and beta in {0, +-1, +-2, +-0.5}: the
+    exact rational result (Fractions) is representable in binary64, so the
+    oracle must reproduce it exactly; NaN sentinels in the padding rows of C
+    must be untouched, and NaN padding of A and B must never be read."""
+    g = _rng(seed)
+    scal = [0.0, 1.0, -1.0, 2.0, -2.0, 0.5, -0.5]
+    for m, n, k in itertools.product(sizes, sizes, sizes):
+        for ta, tb in itertools.product(TRANS, TRANS):
+            pad = pads[(m + n + k) % len(pads)]
+            ar, ac = (m, k) if ta == "N" else (k, m)
+            br, bc = (k, n) if tb == "N" else (n, k)
+            A, lda = _colmajor_padded(g, ar, ac, pad)
+            B, ldb = _colmajor_padded(g, br, bc, pad)
+            C, ldc = _colmajor_padded(g, m, n, pad)
+            alpha = scal[int(g.integers(len(scal)))]
+            beta = scal[int(g.integers(len(scal)))]
+            opA, opB = _op(A, ta, m, k), _op(B, tb, k, n)
+            exp = C.copy()
+            quick = (alpha == 0.0 or k == 0) and beta == 1.0
+            for i in range(m):
+                for j in range(n):
+                    if quick:
+                        continue
+                    s = sum((Fraction(opA[i][p]) * Fraction(opB[p][j]) for p in range(k)),
+                            Fraction(0))
+                    v = Fraction(alpha) * s
+                    if beta != 0.0:
+                        v += Fraction(beta) * Fraction(C[i, j])
+                    exp[i, j] = float(v)
+            got = C.copy(order="F")
+            oracle.dgemm_raw(ta, tb, m, n, k, alpha, A.ravel(order="F"), lda,
+                             B.ravel(order="F"), ldb, beta, got_flat := got.ravel(order="F"),
+                             ldc, lib=lib)
+            got = got_flat.reshape(got.shape, order="F")
+            ok = np.array_equal(got, exp, equal_nan=True)
+            assert ok, f"exact mismatch m={m} n={n} k={k} {ta}{tb} alpha={alpha} beta={beta}"
+
+
+def pin_dgemm_lowercase_and_conj_flags(lib, seed=12):
+    """'n'/'t'/'c'/'C' behave as 'N'/'T'/'T'/'T' for real data."""
+    g = _rng(seed)
+    m, n, k = 5, 4, 3
+    for up, variants in (("N", "n"), ("T", "tcC")):
+        for low in variants:
+            ar, ac = (m, k) if up == "N" else (k, m)
+            A, lda = _colmajor_padded(g, ar, ac, 0)
+            B, ldb = _colmajor_padded(g, k, n, 0)
+            C0, ldc = _colmajor_padded(g, m, n, 0)
+            c1, c2 = C0.ravel(order="F").copy(), C0.ravel(order="F").copy()
+            oracle.dgemm_raw(up, "N", m, n, k, 1.0, A.ravel(order="F"), lda, B.ravel(order="F"),
+                             ldb, 1.0, c1, ldc, lib=lib)
+            oracle.dgemm_raw(low, "n", m, n, k, 1.0, A.ravel(order="F"), lda, B.ravel(order="F"),
+                             ldb, 1.0, c2, ldc, lib=lib)
+            assert np.array_equal(c1, c2), f"flag {low!r} differs from {up!r}"
+
+
+def pin_dgemm_closed_forms(lib, seed=13):
+    """Identity, permutation, all-ones and single non-zero factors."""
+    g = _rng(seed)
+    m = n = k = 7
+    for ta, tb in itertools.product(TRANS, TRANS):
+        # identity left factor: C = alpha*op(B) + beta*C, exact for alpha, beta powers of two
+        B, ldb = _colmajor_padded(g, k if tb == "N" else n, n if tb == "N" else k, 2,
+                                  integer=False)
+        C, ldc = _colmajor_padded(g, m, n, 1, integer=False)
+        I = np.asfortranarray(np.eye(m))
+        got = C.copy(order="F")
+        oracle.dgemm(ta, tb, 2.0, I, B[: (k if tb == "N" else n)], 0.5, got[:m], lib=lib)
+        opB = B[:k, :n] if tb == "N" else B[:n, :k].T
+        assert np.array_equal(got[:m, :n], 2.0 * opB + 0.5 * C[:m, :n]), f"identity {ta}{tb}"
+        assert np.isnan(got[m:]).all(), "padding rows touched"
+        # permutation: op(A) = P permutes the rows of op(B) exactly
+        perm = g.permutation(m)
+        P = np.zeros((m, k))
+        P[np.arange(m), perm] = 1.0
+        Ast = np.asfortranarray(P if ta == "N" else P.T)
+        got = np.zeros((m, n), order="F")
+        oracle.dgemm(ta, tb, 1.0, Ast, B[: (k if tb == "N" else n)], 0.0, got, lib=lib)
+        assert np.array_equal(got, opB[perm, :]), f"permutation {ta}{tb}"
+        # all-ones: every entry equals alpha*k + beta*c0
+        ones_a = np.ones((m, k) if ta == "N" else (k, m), order="F")
+        ones_b = np.ones((k, n) if tb == "N" else (n, k), order="F")
+        C0 = np.asfortranarray(g.integers(-4, 5, size=(m, n)).astype(np.float64))
+        got = C0.copy(order="F")
+        oracle.dgemm(ta, tb, -2.0, ones_a, ones_b, 3.0, got, lib=lib)
+        assert np.array_equal(got, -2.0 * k + 3.0 * C0), f"all-ones {ta}{tb}"
+        # single non-zero op(A) = e_i e_p^T selects row p of op(B) into row i
+        i0, p0 = 2, 5
+        E = np.zeros((m, k))
+        E[i0, p0] = 1.0
+        Est = np.asfortranarray(E if ta == "N" else E.T)
+        got = np.zeros((m, n), order="F")
+        oracle.dgemm(ta, tb, 1.0, Est, B[: (k if tb == "N" else n)], 0.0, got, lib=lib)
+        expct = np.zeros((m, n))
+        expct[i0] = opB[p0]
+        assert np.array_equal(got, expct), f"single non-zero {ta}{tb}"
+
+
+def pin_dgemm_transposition_rule(lib, seed=14):
+    """dgemm(T,T,A,B) equals (dgemm(N,N,B,A))^T bit for bit on integer data
+    (the transposition rule used for the 'TT' kernel of variant 'D', Sec. 2.2)."""
+    g = _rng(seed)
+    for m, n, k in [(3, 5, 4), (8, 2, 9), (1, 6, 1)]:
+        A = np.asfortranarray(g.integers(-4, 5, size=(k, m)).astype(np.float64))  # op(A) = A^T
+        B = np.asfortranarray(g.integers(-4, 5, size=(n, k)).astype(np.float64))  # op(B) = B^T
+        C1 = np.zeros((m, n), order="F")
+        oracle.dgemm("T", "T", 1.0, A, B, 0.0, C1, lib=lib)
+        C2 = np.zeros((n, m), order="F")
+        oracle.dgemm("N", "N", 1.0, B, A, 0.0, C2, lib=lib)
+        assert np.array_equal(C1, C2.T)
+
+
+def pin_dgemm_scipy(lib, seed=15):
+    """Random U[-1,1) data against SciPy's dgemm (OpenBLAS), all trans cases."""
+    from scipy.linalg import blas
+    g = _rng(seed)
+    for m, n, k in [(17, 9, 33), (32, 32, 32), (5, 40, 3), (64, 48, 80)]:
+        for ta, tb in itertools.product(TRANS, TRANS):
+            A = np.asfortranarray(g.uniform(-1, 1, size=(m, k) if ta == "N" else (k, m)))
+            B = np.asfortranarray(g.uniform(-1, 1, size=(k, n) if tb == "N" else (n, k)))
+            C = np.asfortranarray(g.uniform(-1, 1, size=(m, n)))
+            ref = blas.dgemm(0.75, A, B, beta=-1.25, c=C.copy(order="F"),
+                             trans_a=int(ta == "T"), trans_b=int(tb == "T"))
+            got = C.copy(order="F")
+            oracle.dgemm(ta, tb, 0.75, A, B, -1.25, got, lib=lib)
+            err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            assert err <= 1e-14, f"scipy mismatch {ta}{tb} {m}x{n}x{k}: {err}"
+
+
+def pin_dgemm_special_scalars(lib, seed=16):
+    """beta = 0 never reads C (NaN in C does not propagate); alpha = 0 and
+    k = 0 never read A, B; quick return with beta = 1 leaves C untouched."""
+    g = _rng(seed)
+    m, n, k = 4, 3, 5
+    A = np.asfortranarray(g.uniform(-1, 1, size=(m, k)))
+    B = np.asfortranarray(g.uniform(-1, 1, size=(k, n)))
+    C = np.full((m, n), np.nan, order="F")
+    oracle.dgemm("N", "N", 1.0, A, B, 0.0, C, lib=lib)
+    assert np.isfinite(C).all(), "beta = 0 must not read C"
+    An = np.full((m, k), np.nan, order="F")
+    Bn = np.full((k, n), np.nan, order="F")
+    C0 = np.asfortranarray(g.uniform(-1, 1, size=(m, n)))
+    C = C0.copy(order="F")
+    oracle.dgemm("N", "N", 0.0, An, Bn, 2.0, C, lib=lib)
+    assert np.array_equal(C, 2.0 * C0), "alpha = 0 must give beta*C without reading A, B"
+    C = C0.copy(order="F")
+    oracle.dgemm("N", "N", 0.0, An, Bn, 0.0, C, lib=lib)
+    assert np.array_equal(C, np.zeros((m, n))), "alpha = beta = 0 gives zeros"
+    C = np.full((m, n), np.nan, order="F")
+    oracle.dgemm("N", "N", 0.0, An, Bn, 1.0, C, lib=lib)
+    assert np.isnan(C).all(), "quick return must leave C untouched"
+    C = C0.copy(order="F")
+    oracle.dgemm_raw("N", "N", m, n, 0, 1.0, An.ravel(order="F"), m, Bn.ravel(order="F"), 1,
+                     -0.5, cf := C.ravel(order="F"), m, lib=lib)
+    assert np.array_equal(cf.reshape((m, n), order="F"), -0.5 * C0), "k = 0 gives beta*C"
+
+
+def pin_dgemm_batched_matches_single(lib, seed=17):
+    """The OpenMP batched entry equals a loop of single calls bit for bit,
+    with strides larger than the matrices (gaps hold NaN)."""
+    g = _rng(seed)
+    m, n, k, batch = 6, 5, 7, 9
+    lda, ldb, ldc = m + 1, k + 2, m + 3
+    sA, sB, sC = lda * k + 5, ldb * k + 1, ldc * n + 4  # B is stored n x k (op(B) = B^T)
+    A = g.uniform(-1, 1, size=sA * batch)
+    B = g.uniform(-1, 1, size=sB * batch)
+    C = g.uniform(-1, 1, size=sC * batch)
+    C1 = C.copy()
+    oracle.dgemm_strided_batched("N", "T", m, n, k, 1.5, A, lda, sA, B, ldb, sB, -1.0, C1, ldc, sC,
+                                 batch, nthreads=4, lib=lib)
+    # op(B) = B^T needs B stored n x k: use ldb >= n (here k+2 >= n)
+    C2 = C.copy()
+    for b in range(batch):
+        cv = C2[b * sC:(b + 1) * sC]
+        oracle.dgemm_raw("N", "T", m, n, k, 1.5, A[b * sA:(b + 1) * sA], lda,
+                         B[b * sB:(b + 1) * sB], ldb, -1.0, cv, ldc, lib=lib)
+    assert np.array_equal(C1, C2)
+
+
+# ----------------------------------------------------------------------------
+# dpotrf 'L'
+# ----------------------------------------------------------------------------
+
+def _spd(g, n):
+    M = g.uniform(-1, 1, size=(n, n))
+    S = M @ M.T
+    S = 0.5 * (S + S.T) + n * np.eye(n)
+    return np.asfortranarray(S)
+
+
+def pin_potrf_info_closed_form(lib, seed=21):
+    """SPD A with a_jj := -1: columns p < j never read a_jj and the pivot of
+    column j is -1 - sum l_jp^2 <= -1, so info = j+1 for any correct algorithm."""
+    g = _rng(seed)
+    for n in (1, 2, 5, 16, 33):
+        for j in sorted({0, n - 1, int(g.integers(0, n))}):
+            A = _spd(g, n)
+            A[j, j] = -1.0
+            info = oracle.dpotrf_l(A, lib=lib)
+            assert info == j + 1, f"n={n} j={j}: info {info}"
+
+
+def pin_potrf_nan_zero_tiny(lib):
+    """NaN and zero pivots fail (info = j+1); a tiny positive pivot passes."""
+    for bad, expect_fail in ((np.nan, True), (0.0, True), (-0.0, True), (1e-300, False)):
+        A = np.asfortranarray(np.eye(4))
+        A[2, 2] = bad
+        info = oracle.dpotrf_l(A, lib=lib)
+        assert (info == 3) if expect_fail else (info == 0), f"pivot {bad}: info {info}"
+    A = np.asfortranarray(np.eye(3))
+    A[1, 1] = np.nan
+    A[2, 1] = 5.0
+    assert oracle.dpotrf_l(A, lib=lib) == 2
+
+
+def pin_potrf_exact_integer_factor(lib, seed=22):
+    """A = L0 L0^T, L0 integer lower with diagonal in {1, 2, 4} and
+    off-diagonal in [-3, 3]: every intermediate is an integer, square roots
+    are of perfect squares and divisions are by powers of two, so the factor
+    is L0 exactly."""
+    g = _rng(seed)
+    for n in (1, 3, 8, 17, 40, 64):
+        L0 = np.tril(g.integers(-3, 4, size=(n, n)), -1) + np.diag(g.choice([1, 2, 4], size=n))
+        A = np.asfortranarray((L0 @ L0.T).astype(np.float64))
+        assert np.abs(L0 @ L0.T).max() < 2 ** 50
+        info = oracle.dpotrf_l(A, lib=lib)
+        assert info == 0
+        assert np.array_equal(np.tril(A), L0.astype(np.float64)), f"n={n}"
+
+
+def pin_potrf_identity_and_diagonal(lib):
+    A = np.asfortranarray(np.eye(6))
+    assert oracle.dpotrf_l(A, lib=lib) == 0 and np.array_equal(A, np.eye(6))
+    d = np.array([1.0, 4.0, 9.0, 0.25, 16.0, 2.25])
+    A = np.asfortranarray(np.diag(d))
+    assert oracle.dpotrf_l(A, lib=lib) == 0
+    assert np.array_equal(A, np.diag(np.sqrt(d)))
+
+
+def pin_potrf_golden(lib):
+    """Textbook 3x3 and Pascal n=8 fixtures, plus Pascal up to n=25 from the
+    binomial closed form (all intermediates are integers below 2^53)."""
+    for name in ("chol3_textbook.txt", "pascal8_chol.txt"):
+        A, L = _load_pair(name)
+        X = np.asfortranarray(A.copy())
+        assert oracle.dpotrf_l(X, lib=lib) == 0
+        assert np.array_equal(np.tril(X), L), name
+    for n in (12, 25):
+        P = np.array([[math.comb(i + j, i) for j in range(n)] for i in range(n)], dtype=np.float64)
+        L = np.array([[math.comb(i, j) for j in range(n)] for i in range(n)], dtype=np.float64)
+        X = np.asfortranarray(P)
+        assert oracle.dpotrf_l(X, lib=lib) == 0
+        assert np.array_equal(np.tril(X), L), f"pascal {n}"
+
+
+def pin_potrf_small_closed_forms(lib, seed=23):
+    """n = 1: l = sqrt(a).  n = 2: l11 = sqrt(a11), l21 = a21/l11,
+    l22 = sqrt(a22 - l21^2); the oracle evaluates exactly these operations."""
+    g = _rng(seed)
+    for _ in range(20):
+        a = float(g.uniform(0.1, 10))
+        X = np.asfortranarray([[a]])
+        assert oracle.dpotrf_l(X, lib=lib) == 0 and X[0, 0] == math.sqrt(a)
+        A = _spd(g, 2)
+        X = A.copy(order="F")
+        assert oracle.dpotrf_l(X, lib=lib) == 0
+        l11 = math.sqrt(A[0, 0])
+        l21 = A[1, 0] / l11
+        l22 = math.sqrt(A[1, 1] - l21 * l21)
+        assert X[0, 0] == l11 and X[1, 0] == l21 and X[1, 1] == l22
+
+
+def pin_potrf_lapack_and_residual(lib, seed=24):
+    """Against LAPACK dpotrf (SciPy) and the reconstruction residual, computed
+    in extended precision, on the sweep's SPD recipe."""
+    from scipy.linalg import lapack
+    g = _rng(seed)
+    for n in (8, 16, 31, 64, 100):
+        A = _spd(g, n)
+        X = A.copy(order="F")
+        info = oracle.dpotrf_l(X, lib=lib)
+        ref, rinfo = lapack.dpotrf(A.copy(order="F"), lower=1, clean=1)
+        assert info == rinfo == 0
+        L = np.tril(X)
+        err = np.linalg.norm(L - ref) / np.linalg.norm(ref)
+        assert err <= 1e-13, f"n={n} lapack diff {err}"
+        Ll = L.astype(np.longdouble)
+        res = np.sqrt(((A.astype(np.longdouble) - Ll @ Ll.T) ** 2).sum()) / np.sqrt(
+            (A.astype(np.longdouble) ** 2).sum())
+        assert float(res) <= 1e-14, f"n={n} residual {float(res)}"
+        # LAPACK's info convention on a failing instance
+        A[n // 2, n // 2] = -1.0
+        _, rinfo = lapack.dpotrf(A.copy(order="F"), lower=1)
+        assert oracle.dpotrf_l(A.copy(order="F"), lib=lib) == rinfo == n // 2 + 1
+
+
+def pin_potrf_upper_untouched(lib, seed=25):
+    """The strict upper triangle (NaN sentinels) and ld padding stay bit-identical."""
+    g = _rng(seed)
+    n, ld = 12, 15
+    A = np.full((ld, n), np.nan, order="F")
+    A[:n, :n] = _spd(g, n)
+    A[:n, :n][np.triu_indices(n, 1)] = np.nan
+    flat = A.ravel(order="F").copy()
+    info = oracle.dpotrf_l_raw(n, flat, ld, lib=lib)
+    X = flat.reshape(A.shape, order="F")
+    assert info == 0
+    up = np.triu_indices(n, 1)
+    assert np.isnan(X[:n, :n][up]).all() and np.isnan(X[n:]).all()
+    assert np.isfinite(np.tril(X[:n, :n])).all()
+
+
+def pin_potrf_batched_matches_single(lib, seed=26):
+    g = _rng(seed)
+    n, batch, ld = 9, 11, 10
+    s = ld * n + 3
+    A = np.full(s * batch, np.nan)
+    for b in range(batch):
+        blk = np.full((ld, n), np.nan, order="F")
+        blk[:n] = _spd(g, n)
+        A[b * s:b * s + ld * n] = blk.ravel(order="F")
+    A[5 * s + 3 * ld + 3] = -1.0  # instance 5, a_33 = -1 -> info 4
+    A1 = A.copy()
+    info = oracle.dpotrf_l_strided_batched(n, A1, ld, s, batch, nthreads=4, lib=lib)
+    A2 = A.copy()
+    info2 = [oracle.dpotrf_l_raw(n, A2[b * s:(b + 1) * s], ld, lib=lib) for b in range(batch)]
+    assert list(info) == info2 and info[5] == 4 and sum(info) == 4
+    assert np.array_equal(A1, A2, equal_nan=True)
+
+
+# ----------------------------------------------------------------------------
+# Cholesky adjoint
+# ----------------------------------------------------------------------------
+
+def _chol(A, lib):
+    X = np.asfortranarray(A.copy())
+    info = oracle.dpotrf_l(X, lib=lib)
+    assert info == 0
+    return np.tril(X)
+
+
+def pin_adjoint_logdet(lib, seed=31):
+    """f = log det A = 2 sum log l_ii has Lbar = diag(2 / l_ii), for which
+    Phi(L^T Lbar) = I and the gradient is A^{-1} (numpy.linalg.inv)."""
+    g = _rng(seed)
+    for n in (1, 4, 16, 37):
+        A = _spd(g, n)
+        L = _chol(A, lib)
+        Lbar = np.diag(2.0 / np.diag(L))
+        Ab = oracle.dpotrf_l_adjoint(L, Lbar, lib=lib)
+        ref = np.linalg.inv(A)
+        err = np.linalg.norm(Ab - ref) / np.linalg.norm(ref)
+        assert err <= 1e-12, f"n={n}: {err}"
+
+
+def pin_adjoint_n1(lib):
+    for a, lb in ((4.0, 3.0), (2.0, -1.0), (0.25, 0.5)):
+        L = np.array([[math.sqrt(a)]])
+        Ab = oracle.dpotrf_l_adjoint(L, np.array([[lb]]), lib=lib)
+        assert abs(Ab[0, 0] - lb / (2.0 * math.sqrt(a))) <= 1e-15 * abs(Ab[0, 0])
+
+
+def pin_adjoint_finite_differences(lib, seed=32, h=1e-6):
+    """Central differences of f(A) = <W, chol(A)> along symmetric directions."""
+    g = _rng(seed)
+    for n in (3, 10, 24):
+        A = _spd(g, n)
+        W = np.tril(g.uniform(-1, 1, size=(n, n)))
+        L = _chol(A, lib)
+        Ab = oracle.dpotrf_l_adjoint(L, W, lib=lib)
+        assert np.array_equal(Ab, Ab.T), "Abar must be symmetric"
+        for _ in range(5):
+            D = g.uniform(-1, 1, size=(n, n))
+            D = 0.5 * (D + D.T)
+            fp = np.sum(W * _chol(A + h * D, lib))
+            fm = np.sum(W * _chol(A - h * D, lib))
+            fd = (fp - fm) / (2 * h)
+            an = np.sum(Ab * D)
+            assert abs(fd - an) <= 1e-6 * (abs(fd) + 1e-300) + 1e-9, f"n={n}: fd {fd} vs {an}"
+
+
+ALL_PINS = [
+    pin_dgemm_exact_bruteforce,
+    pin_dgemm_lowercase_and_conj_flags,
+    pin_dgemm_closed_forms,
+    pin_dgemm_transposition_rule,
+    pin_dgemm_scipy,
+    pin_dgemm_special_scalars,
+    pin_dgemm_batched_matches_single,
+    pin_potrf_info_closed_form,
+    pin_potrf_nan_zero_tiny,
+    pin_potrf_exact_integer_factor,
+    pin_potrf_identity_and_diagonal,
+    pin_potrf_golden,
+    pin_potrf_small_closed_forms,
+    pin_potrf_lapack_and_residual,
+    pin_potrf_upper_untouched,
+    pin_potrf_batched_matches_single,
+    pin_adjoint_logdet,
+    pin_adjoint_n1,
+    pin_adjoint_finite_differences,
+]
