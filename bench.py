@@ -1,0 +1,463 @@
+#!/usr/bin/env python3
+"""Batched FP64 dgemm / dpotrf('L') throughput on one MI355X.
+
+One step is one pass of the whole hot path over resident synthetic inputs:
+  * the square dgemm sweep, m = n = k in {4, 8, 12, 16, 24, 32, 48, 64, 96,
+    128, 192, 256, 300}, all four trans cases, alpha = beta = 1, lda = m,
+    batch per size such that A + B + C hold about 1 GiB, strided contiguous;
+  * the dpotrf 'L' sweep, n in {8, 16, 32, 64, 128, 192, 256}, batch 4096,
+    A = M M^T + n I with one non-SPD instance (a_jj = -1) per size.
+Every call goes through the C ABI of libmi355blas.so on torch's current
+stream; per-launch durations come from events recorded on that stream.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W]
+  python bench.py --crossover     # direct vs packed dgemm at every sweep size
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "batched FP64 GFLOP/s vs n (dgemm, dpotrf) & % FP64 peak; fused vs plain"
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector and matrix)
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+RIDGE = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def gemm_work(n, batch):
+    """(flops, algorithmic bytes) of one square call with beta != 0."""
+    return 2.0 * n ** 3 * batch, 8.0 * 4 * n * n * batch
+
+
+def potrf_work(n, batch):
+    """(flops n^3/3, bytes: lower triangle read + written, plus info)."""
+    return n ** 3 / 3.0 * batch, 8.0 * n * (n + 1) * batch + 4.0 * batch
+
+
+class Timer:
+    """Per-launch event pairs on the launch stream."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.rec = []
+
+    def around(self, key, fn):
+        t = self.torch
+        e0 = t.cuda.Event(enable_timing=True)
+        e1 = t.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        self.rec.append((key, e0, e1))
+
+    def collect(self):
+        out = {}
+        for key, e0, e1 in self.rec:
+            out.setdefault(key, []).append(e0.elapsed_time(e1))
+        self.rec = []
+        return out
+
+
+def source_digest(paths):
+    h = hashlib.sha256()
+    for p in sorted(paths):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, per_launch_bytes):
+    """HBM traffic measured with rocprofv3 counters for this kernel, if the
+    committed measurement was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except Exception:
+        return None
+    ent = data.get(kernel)
+    if not ent:
+        return None
+    csrc = os.path.join(ROOT, "paper_1902_08115_amd", "csrc")
+    srcs = [os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".h"))]
+    if ent.get("source_digest") != source_digest(srcs):
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def build_inputs(torch, inputs, args):
+    gemm = []
+    for si, n in enumerate(args.gemm_sizes):
+        batch = inputs.gemm_sweep_batch(n)
+        s = inputs.seed_for(1, inputs.GEMM_SWEEP_SIZES.index(n))
+        A = inputs.torch_colmajor(batch, n, n, seed=s)
+        B = inputs.torch_colmajor(batch, n, n, seed=s + 1)
+        C = inputs.torch_colmajor(batch, n, n, seed=s + 2)
+        gemm.append((n, batch, A, B, C))
+    potrf = []
+    for n in args.potrf_sizes:
+        si = inputs.POTRF_SWEEP_SIZES.index(n)
+        batch = args.potrf_batch
+        master = inputs.torch_spd(batch, n, seed=inputs.seed_for(2, si))
+        rs = np.random.Generator(np.random.PCG64(inputs.seed_for(2, si)))
+        bad_b, bad_j = int(rs.integers(0, batch)), int(rs.integers(0, n))
+        master[bad_b, bad_j, bad_j] = -1.0
+        copies = [master.clone() for _ in range(args.copies)]
+        info = torch.empty(batch, dtype=torch.int32, device="cuda")
+        potrf.append((n, batch, master, copies, info, (bad_b, bad_j)))
+    torch.cuda.synchronize()
+    return gemm, potrf
+
+
+def run_step(step, gemm, potrf, _lib, stream, timer, restore_counter):
+    sh = stream.cuda_stream
+    for (n, batch, A, B, C) in gemm:
+        for trans in ("NN", "NT", "TN", "TT"):
+            ta, tb = trans
+
+            def call(ta=ta, tb=tb, n=n, batch=batch, A=A, B=B, C=C):
+                st = _lib.dgemm_strided_batched(ta, tb, n, n, n, 1.0, A.data_ptr(), n, n * n,
+                                                B.data_ptr(), n, n * n, 1.0, C.data_ptr(), n,
+                                                n * n, batch, sh)
+                if st != 0:
+                    raise RuntimeError(f"mb_dgemm_strided_batched {trans} n={n}: status {st}")
+            if timer is None:
+                call()
+            else:
+                timer.around(("dgemm", trans, n), call)
+    for (n, batch, master, copies, info, _) in potrf:
+        c = step % len(copies)
+        if step >= len(copies):  # this copy was factored before: restore it (timed)
+            copies[c].copy_(master)
+            restore_counter[0] += 2 * master.numel() * 8
+
+        def callp(n=n, batch=batch, X=copies[c], info=info):
+            st = _lib.dpotrf_strided_batched("L", n, X.data_ptr(), n, n * n, info.data_ptr(),
+                                             batch, sh)
+            if st != 0:
+                raise RuntimeError(f"mb_dpotrf_strided_batched n={n}: status {st}")
+        if timer is None:
+            callp()
+        else:
+            timer.around(("dpotrf", "L", n), callp)
+
+
+def cpu_baseline(torch, oracle, gemm, potrf, flops_per_case):
+    """The oracle on the host cores, on a bounded prefix of each case."""
+    total_flops = 0.0
+    total_time = 0.0
+    parts = []
+    for (n, batch, A, B, C) in gemm:
+        cnt = int(max(1, min(batch, flops_per_case // (2 * n ** 3))))
+        a = A[:cnt].transpose(1, 2).contiguous().cpu().numpy().ravel()
+        b = B[:cnt].transpose(1, 2).contiguous().cpu().numpy().ravel()
+        c0 = C[:cnt].transpose(1, 2).contiguous().cpu().numpy().ravel()
+        for trans in ("NN", "NT", "TN", "TT"):
+            c = c0.copy()
+            t0 = time.perf_counter()
+            oracle.dgemm_strided_batched(trans[0], trans[1], n, n, n, 1.0, a, n, n * n, b, n,
+                                         n * n, 1.0, c, n, n * n, cnt)
+            total_time += time.perf_counter() - t0
+            total_flops += 2.0 * n ** 3 * cnt
+        parts.append(f"dgemm n={n}: {cnt} instances x 4 trans")
+    for (n, batch, master, copies, info, _) in potrf:
+        cnt = int(max(1, min(batch, flops_per_case // max(1, n ** 3 // 3))))
+        x = master[:cnt].transpose(1, 2).contiguous().cpu().numpy().ravel()
+        t0 = time.perf_counter()
+        oracle.dpotrf_l_strided_batched(n, x, n, n * n, cnt)
+        total_time += time.perf_counter() - t0
+        total_flops += n ** 3 / 3.0 * cnt
+        parts.append(f"dpotrf n={n}: {cnt} instances")
+    return {
+        "value": total_flops / total_time / 1e9,
+        "unit": "GFLOP/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "seconds": round(total_time, 2),
+        "sample": "leading instances of every sweep case, about "
+                  f"{flops_per_case / 1e9:.1f} GFLOP per case: " + "; ".join(parts),
+    }
+
+
+def parity_spot_check(torch, _lib, oracle, gemm, potrf, stream):
+    """Untimed: one more call per case on sampled instances vs the oracle."""
+    sh = stream.cuda_stream
+    worst_gemm = 0.0
+    for (n, batch, A, B, C) in gemm:
+        if n not in (4, 12, 64, 192, 300):
+            continue
+        idx = torch.tensor([0, batch // 2, batch - 1], device="cuda")
+        for trans in ("NN", "NT", "TN", "TT"):
+            a0 = A[idx].cpu().numpy()
+            b0 = B[idx].cpu().numpy()
+            c0 = C[idx].cpu().numpy()
+            st = _lib.dgemm_strided_batched(trans[0], trans[1], n, n, n, 1.0, A.data_ptr(), n,
+                                            n * n, B.data_ptr(), n, n * n, 1.0, C.data_ptr(), n,
+                                            n * n, batch, sh)
+            assert st == 0
+            cg = C[idx].cpu().numpy()
+            for j in range(3):
+                cr = np.asfortranarray(c0[j].copy())
+                oracle.dgemm(trans[0], trans[1], 1.0, np.asfortranarray(a0[j]),
+                             np.asfortranarray(b0[j]), 1.0, cr)
+                worst_gemm = max(worst_gemm, np.linalg.norm(cg[j] - cr) / np.linalg.norm(cr))
+    worst_res = 0.0
+    info_ok = True
+    for (n, batch, master, copies, info, (bad_b, bad_j)) in potrf:
+        X = master.clone()
+        st = _lib.dpotrf_strided_batched("L", n, X.data_ptr(), n, n * n, info.data_ptr(), batch,
+                                         sh)
+        assert st == 0
+        inf = info.cpu().numpy()
+        exp = np.zeros(batch, dtype=np.int32)
+        exp[bad_b] = bad_j + 1
+        info_ok = info_ok and bool(np.array_equal(inf, exp))
+        for b in (0, batch - 1):
+            if b == bad_b:
+                continue
+            a0 = master[b].cpu().numpy().astype(np.longdouble)
+            lg = np.tril(X[b].cpu().numpy()).astype(np.longdouble)
+            r = np.sqrt(((a0 - lg @ lg.T) ** 2).sum() / (a0 ** 2).sum())
+            worst_res = max(worst_res, float(r))
+        del X
+    return {"dgemm_max_rel_err": worst_gemm, "dpotrf_max_residual": worst_res,
+            "dpotrf_info_exact": info_ok, "tolerance": 1e-12,
+            "pass": worst_gemm <= 1e-12 and worst_res <= 1e-12 and info_ok}
+
+
+def crossover(torch, _lib, inputs, args):
+    """Direct vs packed dgemm at every sweep size and trans case."""
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+    rows = []
+    for n in args.gemm_sizes:
+        batch = inputs.gemm_sweep_batch(n)
+        A = inputs.torch_colmajor(batch, n, n, seed=1)
+        B = inputs.torch_colmajor(batch, n, n, seed=2)
+        C = inputs.torch_colmajor(batch, n, n, seed=3)
+        for trans in ("NN", "NT", "TN", "TT"):
+            res = {}
+            for vname, v in (("direct", 1), ("packed", 2)):
+                def call():
+                    st = _lib.dgemm_strided_batched(trans[0], trans[1], n, n, n, 1.0,
+                                                    A.data_ptr(), n, n * n, B.data_ptr(), n,
+                                                    n * n, 1.0, C.data_ptr(), n, n * n, batch,
+                                                    sh, v)
+                    assert st == 0
+                for _ in range(2):
+                    call()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(args.steps):
+                    call()
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / args.steps
+                fl, by = gemm_work(n, batch)
+                res[vname] = {"ms": ms, "gflops": fl / ms / 1e6, "gbps": by / ms / 1e6,
+                              "kernel": _lib.dgemm_kernel_name(trans[0], trans[1], n, n, n, v)}
+            rows.append({"n": n, "trans": trans, "batch": batch, **res,
+                         "faster": min(res, key=lambda k: res[k]["ms"])})
+            log(f"crossover n={n} {trans}: direct {res['direct']['gflops']:.0f} GF/s, "
+                f"packed {res['packed']['gflops']:.0f} GF/s")
+        del A, B, C
+        torch.cuda.empty_cache()
+    print(json.dumps({"crossover": rows}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--copies", type=int, default=None,
+                    help="pristine dpotrf input copies (default: warmup + steps, at most 12)")
+    ap.add_argument("--gemm-sizes", type=str, default=None)
+    ap.add_argument("--potrf-sizes", type=str, default=None)
+    ap.add_argument("--potrf-batch", type=int, default=None)
+    ap.add_argument("--cpu-flops-per-case", type=float, default=1.5e9)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--crossover", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); the "
+              "batched path shards by splitting the batch across GPUs with no exchange, which "
+              "is not run here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1902_08115_amd import _lib, inputs
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+
+    args.gemm_sizes = ([int(x) for x in args.gemm_sizes.split(",")] if args.gemm_sizes
+                       else list(inputs.GEMM_SWEEP_SIZES))
+    args.potrf_sizes = ([int(x) for x in args.potrf_sizes.split(",")] if args.potrf_sizes
+                        else list(inputs.POTRF_SWEEP_SIZES))
+    args.potrf_batch = args.potrf_batch or inputs.POTRF_SWEEP_BATCH
+    if args.copies is None:
+        args.copies = max(1, min(12, args.warmup + args.steps))
+
+    if args.crossover:
+        crossover(torch, _lib, inputs, args)
+        return
+
+    log(f"device {torch.cuda.get_device_name(0)}; generating inputs")
+    gemm, potrf = build_inputs(torch, inputs, args)
+    log("inputs resident")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(torch, oracle, gemm, potrf, args.cpu_flops_per_case)
+        log(f"cpu baseline {cpu['value']:.2f} GFLOP/s on {cpu['cores']} threads "
+            f"({cpu['seconds']} s)")
+
+    stream = torch.cuda.current_stream()
+    restore = [0]
+    for w in range(args.warmup):
+        run_step(w, gemm, potrf, _lib, stream, None, restore)
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    timer = Timer(torch)
+    restore = [0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        run_step(args.warmup + s, gemm, potrf, _lib, stream, timer, restore)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
+    durations = timer.collect()
+
+    # per-call and per-kernel-class accounting
+    per_size = {}
+    classes = {}
+    step_flops = 0.0
+    for (n, batch, *_r) in gemm:
+        fl, by = gemm_work(n, batch)
+        for trans in ("NN", "NT", "TN", "TT"):
+            ms = float(np.mean(durations[("dgemm", trans, n)]))
+            kname = f"{_lib.dgemm_kernel_name(trans[0], trans[1], n, n, n)}_{trans}"
+            per_size[f"dgemm_{trans}_n{n}"] = {
+                "kernel": kname, "batch": batch, "ms": round(ms, 4),
+                "gflops": round(fl / ms / 1e6, 1), "gbps": round(by / ms / 1e6, 1),
+                "roof_frac": round((fl / ms / 1e9) / min(PEAK_FP64_TFLOPS,
+                                                          fl / by * PEAK_HBM_GBS / 1e3), 3)}
+            c = classes.setdefault(kname, {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
+            cnt = len(durations[("dgemm", trans, n)])
+            c["ms"] += ms * cnt
+            c["launches"] += cnt
+            c["flops"] += fl * cnt
+            c["bytes"] += by * cnt
+            step_flops += fl
+    for (n, batch, *_r) in potrf:
+        fl, by = potrf_work(n, batch)
+        ms = float(np.mean(durations[("dpotrf", "L", n)]))
+        kname = _lib.dpotrf_kernel_name(n)
+        per_size[f"dpotrf_n{n}"] = {
+            "kernel": kname, "batch": batch, "ms": round(ms, 4),
+            "gflops": round(fl / ms / 1e6, 1), "gbps": round(by / ms / 1e6, 1),
+            "roof_frac": round((fl / ms / 1e9) / min(PEAK_FP64_TFLOPS,
+                                                      fl / by * PEAK_HBM_GBS / 1e3), 3)}
+        c = classes.setdefault(kname, {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
+        cnt = len(durations[("dpotrf", "L", n)])
+        c["ms"] += ms * cnt
+        c["launches"] += cnt
+        c["flops"] += fl * cnt
+        c["bytes"] += by * cnt
+        step_flops += fl
+
+    kernels = {}
+    for k, c in classes.items():
+        ai = c["flops"] / c["bytes"]
+        bound = "mfma" if ai >= RIDGE else "hbm"
+        avg_ms = c["ms"] / c["launches"]
+        if bound == "mfma":
+            ach = c["flops"] / (c["ms"] * 1e-3) / 1e12
+            peak, unit = PEAK_FP64_TFLOPS, "TFLOP/s"
+        else:
+            ach = c["bytes"] / (c["ms"] * 1e-3) / 1e9
+            peak, unit = PEAK_HBM_GBS, "GB/s"
+        kernels[k] = {"bound": bound, "achieved": round(ach, 2), "peak": peak, "unit": unit,
+                      "frac": round(ach / peak, 4), "avg_launch_ms": round(avg_ms, 4),
+                      "launches_per_step": c["launches"] // args.steps,
+                      "share_of_kernel_time": None, "flops_per_launch": c["flops"] / c["launches"],
+                      "bytes_per_launch": c["bytes"] / c["launches"]}
+    total_kernel_ms = sum(c["ms"] for c in classes.values())
+    for k in kernels:
+        kernels[k]["share_of_kernel_time"] = round(classes[k]["ms"] / total_kernel_ms, 4)
+    dom = max(kernels, key=lambda k: classes[k]["ms"])
+    d = kernels[dom]
+    roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
+                "unit": d["unit"], "frac": d["frac"],
+                "traffic": traffic_for(dom, d["bytes_per_launch"]),
+                "algorithmic_bytes_per_launch": d["bytes_per_launch"],
+                "algorithmic_flops_per_launch": d["flops_per_launch"],
+                "avg_launch_ms": d["avg_launch_ms"]}
+
+    parity = None
+    if not args.no_parity:
+        import oracle
+        log("parity spot check")
+        parity = parity_spot_check(torch, _lib, oracle, gemm, potrf, stream)
+
+    value = step_flops / (ms_per_step * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "square batched dgemm sweep (n in %s, NN/NT/TN/TT, alpha=beta=1, lda=n, "
+                        "batch ~1 GiB of A+B+C per size) + batched dpotrf L sweep (n in %s, "
+                        "batch %d, one non-SPD instance per size)"
+                        % (args.gemm_sizes, args.potrf_sizes, args.potrf_batch),
+            "gemm_sizes": args.gemm_sizes, "potrf_sizes": args.potrf_sizes,
+            "potrf_batch": args.potrf_batch, "potrf_input_copies": args.copies,
+            "restore_bytes_per_step": restore[0] / args.steps,
+            "flops_per_step": step_flops,
+        },
+        "fp64_peak_frac": round(value / (PEAK_FP64_TFLOPS * 1e3), 4),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "per_size": per_size,
+        "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

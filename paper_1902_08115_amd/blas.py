@@ -1,0 +1,136 @@
+"""Torch-facing wrappers of the mi355blas C ABI (memory and streams only).
+
+Tensors must already be column-major FP64 on the GPU: a matrix is a 2-D
+tensor with stride(-2) == 1 and stride(-1) == ld >= rows; a strided batch is
+a 3-D tensor (batch, rows, cols) with the same per-instance layout and
+stride(0) as the instance stride.  Nothing is copied or converted behind the
+caller's back: a tensor in any other layout raises.  ``colmajor_empty`` and
+``colmajor_from_numpy`` build conforming tensors.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib
+from ._lib import MbError, VARIANT_AUTO, VARIANT_DIRECT, VARIANT_PACKED  # noqa: F401
+
+
+def _stream(stream) -> int:
+    return (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+
+
+def _layout(X: torch.Tensor, name: str, batched: bool):
+    """Return (ld, instance_stride) of a column-major FP64 CUDA tensor."""
+    if X.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not X.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if X.dim() != (3 if batched else 2):
+        raise ValueError(f"{name} must be {'3' if batched else '2'}-D")
+    rows, cols = X.shape[-2], X.shape[-1]
+    s_r, s_c = X.stride(-2), X.stride(-1)
+    if rows > 1 and s_r != 1:
+        raise ValueError(f"{name} is not column-major (stride(-2) must be 1)")
+    ld = s_c if cols > 1 else max(1, rows, s_c)
+    if ld < max(1, rows):
+        raise ValueError(f"{name}: leading dimension {ld} < rows {rows}")
+    return ld, (X.stride(0) if batched else 0)
+
+
+def _raise(fn, st):
+    if st != _lib.MB_OK:
+        raise MbError(fn, st)
+
+
+def colmajor_empty(batch, rows, cols, ld=None, device="cuda", fill=None):
+    """Uninitialised (or ``fill``-ed) column-major batch tensor (batch, rows, cols)."""
+    ld = max(1, rows) if ld is None else ld
+    base = torch.empty((batch, max(cols, 1), ld), dtype=torch.float64, device=device)
+    if fill is not None:
+        base.fill_(fill)
+    return base.transpose(1, 2)[:, :rows, :cols]
+
+
+def colmajor_from_numpy(X, rows, device="cuda"):
+    """Device copy of a numpy batch in the (batch, cols, ld) column-major
+    buffer layout; returns the (batch, rows, cols) view."""
+    t = torch.from_numpy(X).to(device)
+    return t.transpose(1, 2)[:, :rows, :]
+
+
+def dgemm(transa, transb, alpha, A, B, beta, C, stream=None):
+    """C <= alpha*op(A)*op(B) + beta*C for 2-D column-major tensors."""
+    lda, _ = _layout(A, "A", False)
+    ldb, _ = _layout(B, "B", False)
+    ldc, _ = _layout(C, "C", False)
+    m, n = C.shape
+    k = A.shape[1] if transa in "Nn" else A.shape[0]
+    st = _lib.dgemm(transa, transb, m, n, k, alpha, A.data_ptr(), lda, B.data_ptr(), ldb, beta,
+                    C.data_ptr(), ldc, _stream(stream))
+    _raise("mb_dgemm", st)
+    return C
+
+
+def dgemm_strided_batched(transa, transb, alpha, A, B, beta, C, variant=None, stream=None):
+    """Strided batch over the leading dimension of 3-D column-major tensors."""
+    lda, sA = _layout(A, "A", True)
+    ldb, sB = _layout(B, "B", True)
+    ldc, sC = _layout(C, "C", True)
+    batch, m, n = C.shape
+    k = A.shape[2] if transa in "Nn" else A.shape[1]
+    st = _lib.dgemm_strided_batched(transa, transb, m, n, k, alpha, A.data_ptr(), lda, sA,
+                                    B.data_ptr(), ldb, sB, beta, C.data_ptr(), ldc, sC, batch,
+                                    _stream(stream), variant)
+    _raise("mb_dgemm_strided_batched", st)
+    return C
+
+
+def pointer_array(X: torch.Tensor) -> torch.Tensor:
+    """Device array of the instance base pointers of a batch tensor."""
+    base = X.data_ptr()
+    idx = torch.arange(X.shape[0], dtype=torch.int64)
+    return (base + idx * X.stride(0) * 8).to(X.device)
+
+
+def dgemm_batched(transa, transb, m, n, k, alpha, Aptr, lda, Bptr, ldb, beta, Cptr, ldc, batch,
+                  variant=None, stream=None):
+    """Pointer-array batch; Aptr/Bptr/Cptr are int64 device tensors of addresses."""
+    st = _lib.dgemm_batched(transa, transb, m, n, k, alpha, Aptr.data_ptr(), lda, Bptr.data_ptr(),
+                            ldb, beta, Cptr.data_ptr(), ldc, batch, _stream(stream), variant)
+    _raise("mb_dgemm_batched", st)
+
+
+def dpotrf(A, info=None, stream=None):
+    """Lower Cholesky in place on a 2-D column-major tensor; returns the
+    device info tensor (shape (1,), int32) -- valid after the stream completes."""
+    lda, _ = _layout(A, "A", False)
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise ValueError("A must be square")
+    if info is None:
+        info = torch.empty(1, dtype=torch.int32, device=A.device)
+    st = _lib.dpotrf("L", n, A.data_ptr(), lda, info.data_ptr(), _stream(stream))
+    _raise("mb_dpotrf", st)
+    return info
+
+
+def dpotrf_strided_batched(A, info=None, stream=None):
+    lda, sA = _layout(A, "A", True)
+    batch, n, n2 = A.shape
+    if n != n2:
+        raise ValueError("A must be square")
+    if info is None:
+        info = torch.empty(max(batch, 1), dtype=torch.int32, device=A.device)[:batch]
+    st = _lib.dpotrf_strided_batched("L", n, A.data_ptr(), lda, sA, info.data_ptr(), batch,
+                                     _stream(stream))
+    _raise("mb_dpotrf_strided_batched", st)
+    return info
+
+
+def dpotrf_batched(Aptr, n, lda, batch, info=None, stream=None):
+    if info is None:
+        info = torch.empty(max(batch, 1), dtype=torch.int32, device=Aptr.device)[:batch]
+    st = _lib.dpotrf_batched("L", n, Aptr.data_ptr(), lda, info.data_ptr(), batch,
+                             _stream(stream))
+    _raise("mb_dpotrf_batched", st)
+    return info

@@ -1,0 +1,301 @@
+// api.hip -- host side of the mi355blas C ABI: argument validation, quick
+// returns, size-class dispatch (Sec. 2.4: a no-pack variant for very small
+// operands, a packed variant above a measured switching point), launch.
+//
+// No call allocates memory, synchronizes or keeps mutable global state.
+#include <limits.h>
+#include <stdint.h>
+
+#include "../../include/mi355blas.h"
+#include "mb_internal.h"
+
+namespace {
+
+using mb::GemmArgs;
+using mb::PotrfArgs;
+
+int trans_code(char t)  // 0 = N, 1 = T, -1 = illegal
+{
+    switch (t) {
+    case 'N': case 'n': return 0;
+    case 'T': case 't': case 'C': case 'c': return 1;
+    default: return -1;
+    }
+}
+
+// Switching point between the direct and the packed kernel families, per
+// trans case (index 2*ta + tb): the direct kernel is used while
+// max(m, n, k) <= the value.  Measured on MI355X with the square sweep of the
+// benchmark (see the dgemm crossover profile).
+constexpr int kCrossover[4] = {8, 8, 8, 8};
+
+int select_variant(int ta, int tb, int m, int n, int k)
+{
+    int mx = m > n ? m : n;
+    mx = mx > k ? mx : k;
+    return mx <= kCrossover[2 * ta + tb] ? MB_VARIANT_DIRECT : MB_VARIANT_PACKED;
+}
+
+int to_status(hipError_t e) { return e == hipSuccess ? MB_OK : MB_ERR_HIP; }
+
+// Shared validation of the dgemm scalar arguments; positions of lda/ldb/ldc
+// differ between the call forms and are passed in.
+int check_gemm(char transa, char transb, int m, int n, int k, int lda, int ldb, int ldc,
+               int pos_lda, int pos_ldb, int pos_ldc)
+{
+    const int ta = trans_code(transa), tb = trans_code(transb);
+    if (ta < 0) return -1;
+    if (tb < 0) return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0) return -5;
+    const int arows = ta ? k : m, brows = tb ? n : k;
+    if (lda < (arows > 1 ? arows : 1)) return -pos_lda;
+    if (ldb < (brows > 1 ? brows : 1)) return -pos_ldb;
+    if (ldc < (m > 1 ? m : 1)) return -pos_ldc;
+    return MB_OK;
+}
+
+int run_gemm(int ta, int tb, GemmArgs &a, int variant, hipStream_t s)
+{
+    if (a.m == 0 || a.n == 0 || a.batch == 0)
+        return MB_OK;
+    if ((a.alpha == 0.0 || a.k == 0) && a.beta == 1.0)
+        return MB_OK;
+    if (a.alpha == 0.0 || a.k == 0)
+        return to_status(mb::launch_gemm_scale(a, s));
+    if (variant == MB_VARIANT_AUTO)
+        variant = select_variant(ta, tb, a.m, a.n, a.k);
+    if (variant == MB_VARIANT_DIRECT)
+        return to_status(mb::launch_gemm_direct(ta, tb, a, s));
+    return to_status(mb::launch_gemm_packed(ta, tb, a, s));
+}
+
+int gemm_strided(char transa, char transb, int m, int n, int k, double alpha, const double *A,
+                 int lda, int64_t strideA, const double *B, int ldb, int64_t strideB, double beta,
+                 double *C, int ldc, int64_t strideC, int batch, int variant, int pos_variant,
+                 hipStream_t stream)
+{
+    int st = check_gemm(transa, transb, m, n, k, lda, ldb, ldc, 8, 11, 15);
+    if (st != MB_OK)
+        return st;
+    if (strideA < 0) return -9;
+    if (strideB < 0) return -12;
+    if (strideC < 0) return -16;
+    if (batch < 0) return -17;
+    if (variant < MB_VARIANT_AUTO || variant > MB_VARIANT_PACKED) return -pos_variant;
+    if (batch > 1 && m > 0 && n > 0 && strideC < (int64_t)ldc * (n - 1) + m) return -16;
+    const bool work = m > 0 && n > 0 && batch > 0 && !((alpha == 0.0 || k == 0) && beta == 1.0);
+    if (work) {
+        const bool reads_ab = alpha != 0.0 && k > 0;
+        if (reads_ab && !A) return -7;
+        if (reads_ab && !B) return -10;
+        if (!C) return -14;
+    }
+    GemmArgs a{};
+    a.m = m; a.n = n; a.k = k; a.alpha = alpha; a.beta = beta;
+    a.A = A; a.sA = strideA; a.lda = lda;
+    a.B = B; a.sB = strideB; a.ldb = ldb;
+    a.C = C; a.sC = strideC; a.ldc = ldc;
+    a.batch = batch;
+    return run_gemm(trans_code(transa), trans_code(transb), a, variant, stream);
+}
+
+int gemm_array(char transa, char transb, int m, int n, int k, double alpha,
+               const double *const *Aarray, int lda, const double *const *Barray, int ldb,
+               double beta, double *const *Carray, int ldc, int batch, int variant,
+               int pos_variant, hipStream_t stream)
+{
+    int st = check_gemm(transa, transb, m, n, k, lda, ldb, ldc, 8, 10, 13);
+    if (st != MB_OK)
+        return st;
+    if (batch < 0) return -14;
+    if (variant < MB_VARIANT_AUTO || variant > MB_VARIANT_PACKED) return -pos_variant;
+    const bool work = m > 0 && n > 0 && batch > 0 && !((alpha == 0.0 || k == 0) && beta == 1.0);
+    if (work) {
+        const bool reads_ab = alpha != 0.0 && k > 0;
+        if (reads_ab && !Aarray) return -7;
+        if (reads_ab && !Barray) return -9;
+        if (!Carray) return -12;
+    }
+    GemmArgs a{};
+    a.m = m; a.n = n; a.k = k; a.alpha = alpha; a.beta = beta;
+    a.Aarr = Aarray; a.lda = lda;
+    a.Barr = Barray; a.ldb = ldb;
+    a.Carr = Carray; a.ldc = ldc;
+    a.batch = batch;
+    return run_gemm(trans_code(transa), trans_code(transb), a, variant, stream);
+}
+
+int uplo_check(char uplo)  // 0 lower, 1 upper (unsupported), -1 illegal
+{
+    switch (uplo) {
+    case 'L': case 'l': return 0;
+    case 'U': case 'u': return 1;
+    default: return -1;
+    }
+}
+
+int run_potrf(PotrfArgs &a, hipStream_t s)
+{
+    if (a.batch == 0)
+        return MB_OK;
+    if (a.n == 0)
+        return to_status(mb::launch_fill_info(a.info, a.batch, s));
+    return to_status(mb::launch_potrf_lower(a, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+int mb_dgemm(char transa, char transb, int m, int n, int k, double alpha, const double *A,
+             int lda, const double *B, int ldb, double beta, double *C, int ldc,
+             hipStream_t stream)
+{
+    int st = check_gemm(transa, transb, m, n, k, lda, ldb, ldc, 8, 10, 13);
+    if (st != MB_OK)
+        return st;
+    const bool work = m > 0 && n > 0 && !((alpha == 0.0 || k == 0) && beta == 1.0);
+    if (work) {
+        const bool reads_ab = alpha != 0.0 && k > 0;
+        if (reads_ab && !A) return -7;
+        if (reads_ab && !B) return -9;
+        if (!C) return -12;
+    }
+    GemmArgs a{};
+    a.m = m; a.n = n; a.k = k; a.alpha = alpha; a.beta = beta;
+    a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.C = C; a.ldc = ldc;
+    a.batch = 1;
+    return run_gemm(trans_code(transa), trans_code(transb), a, MB_VARIANT_AUTO, stream);
+}
+
+int mb_dgemm_strided_batched(char transa, char transb, int m, int n, int k, double alpha,
+                             const double *A, int lda, int64_t strideA, const double *B, int ldb,
+                             int64_t strideB, double beta, double *C, int ldc, int64_t strideC,
+                             int batch, hipStream_t stream)
+{
+    return gemm_strided(transa, transb, m, n, k, alpha, A, lda, strideA, B, ldb, strideB, beta,
+                        C, ldc, strideC, batch, MB_VARIANT_AUTO, 0, stream);
+}
+
+int mb_dgemm_strided_batched_ex(char transa, char transb, int m, int n, int k, double alpha,
+                                const double *A, int lda, int64_t strideA, const double *B,
+                                int ldb, int64_t strideB, double beta, double *C, int ldc,
+                                int64_t strideC, int batch, int variant, hipStream_t stream)
+{
+    return gemm_strided(transa, transb, m, n, k, alpha, A, lda, strideA, B, ldb, strideB, beta,
+                        C, ldc, strideC, batch, variant, 18, stream);
+}
+
+int mb_dgemm_batched(char transa, char transb, int m, int n, int k, double alpha,
+                     const double *const *Aarray, int lda, const double *const *Barray, int ldb,
+                     double beta, double *const *Carray, int ldc, int batch, hipStream_t stream)
+{
+    return gemm_array(transa, transb, m, n, k, alpha, Aarray, lda, Barray, ldb, beta, Carray, ldc,
+                      batch, MB_VARIANT_AUTO, 0, stream);
+}
+
+int mb_dgemm_batched_ex(char transa, char transb, int m, int n, int k, double alpha,
+                        const double *const *Aarray, int lda, const double *const *Barray,
+                        int ldb, double beta, double *const *Carray, int ldc, int batch,
+                        int variant, hipStream_t stream)
+{
+    return gemm_array(transa, transb, m, n, k, alpha, Aarray, lda, Barray, ldb, beta, Carray, ldc,
+                      batch, variant, 15, stream);
+}
+
+int mb_dgemm_select(char transa, char transb, int m, int n, int k)
+{
+    const int ta = trans_code(transa), tb = trans_code(transb);
+    if (ta < 0 || tb < 0)
+        return -1;
+    return select_variant(ta, tb, m, n, k);
+}
+
+const char *mb_dgemm_kernel_name(char transa, char transb, int m, int n, int k, int variant)
+{
+    const int ta = trans_code(transa), tb = trans_code(transb);
+    if (ta < 0 || tb < 0 || m < 0 || n < 0 || k < 0)
+        return "illegal";
+    if (m == 0 || n == 0)
+        return "none";
+    if (k == 0)
+        return "gemm_scale";
+    if (variant == MB_VARIANT_AUTO)
+        variant = select_variant(ta, tb, m, n, k);
+    if (variant == MB_VARIANT_DIRECT)
+        return "gemm_direct";
+    return mb::packed_kernel_name(m, n);
+}
+
+const char *mb_dpotrf_kernel_name(int n)
+{
+    if (n < 0 || n > mb::POTRF_MAX_N)
+        return "unsupported";
+    return mb::potrf_kernel_name(n);
+}
+
+int mb_dpotrf(char uplo, int n, double *A, int lda, int *info, hipStream_t stream)
+{
+    const int u = uplo_check(uplo);
+    if (u < 0) return -1;
+    if (n < 0) return -2;
+    if (lda < (n > 1 ? n : 1)) return -4;
+    if (u == 1) return MB_ERR_UNSUPPORTED;
+    if (n > mb::POTRF_MAX_N) return MB_ERR_UNSUPPORTED;
+    if (n > 0 && !A) return -3;
+    if (!info) return -5;
+    PotrfArgs a{};
+    a.n = n; a.A = A; a.lda = lda; a.info = info; a.batch = 1;
+    return run_potrf(a, stream);
+}
+
+int mb_dpotrf_strided_batched(char uplo, int n, double *A, int lda, int64_t strideA, int *info,
+                              int batch, hipStream_t stream)
+{
+    const int u = uplo_check(uplo);
+    if (u < 0) return -1;
+    if (n < 0) return -2;
+    if (lda < (n > 1 ? n : 1)) return -4;
+    if (strideA < 0) return -5;
+    if (batch < 0) return -7;
+    if (batch > 1 && n > 0 && strideA < (int64_t)lda * (n - 1) + n) return -5;
+    if (u == 1) return MB_ERR_UNSUPPORTED;
+    if (n > mb::POTRF_MAX_N) return MB_ERR_UNSUPPORTED;
+    if (batch > 0 && n > 0 && !A) return -3;
+    if (batch > 0 && !info) return -6;
+    PotrfArgs a{};
+    a.n = n; a.A = A; a.sA = strideA; a.lda = lda; a.info = info; a.batch = batch;
+    return run_potrf(a, stream);
+}
+
+int mb_dpotrf_batched(char uplo, int n, double *const *Aarray, int lda, int *info, int batch,
+                      hipStream_t stream)
+{
+    const int u = uplo_check(uplo);
+    if (u < 0) return -1;
+    if (n < 0) return -2;
+    if (lda < (n > 1 ? n : 1)) return -4;
+    if (batch < 0) return -6;
+    if (u == 1) return MB_ERR_UNSUPPORTED;
+    if (n > mb::POTRF_MAX_N) return MB_ERR_UNSUPPORTED;
+    if (batch > 0 && n > 0 && !Aarray) return -3;
+    if (batch > 0 && !info) return -5;
+    PotrfArgs a{};
+    a.n = n; a.Aarr = Aarray; a.lda = lda; a.info = info; a.batch = batch;
+    return run_potrf(a, stream);
+}
+
+const char *mb_status_string(int status)
+{
+    if (status == MB_OK) return "success";
+    if (status == MB_ERR_HIP) return "HIP runtime or launch failure";
+    if (status == MB_ERR_UNSUPPORTED) return "unsupported argument combination";
+    if (status < 0 && status > -64) return "illegal value of argument -status";
+    return "unknown status";
+}
+
+int mb_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+// gemm_direct.hip -- "direct" batched dgemm for tiny operands.
+//
+// The analogue of the paper's algorithmic variant 'D' (Sec. 2.2, Table 1):
+// every operand is used in place, in its column-major layout, with no packing
+// buffer.  On gfx950 that means operands go straight from global memory (L1/L2)
+// into registers, with no LDS staging and no barriers.  One thread computes
+// RN consecutive entries of one row of C; the threads of a 256-wide workgroup
+// cover several whole instances (tiny m*n) or one slice of an instance.
+// Consecutive lanes own consecutive rows i, so C and a non-transposed A are
+// accessed with unit stride across lanes; op(B) values are shared by all lanes
+// of an instance (broadcast loads).
+#include "mb_internal.h"
+
+namespace mb {
+
+template <bool TA, bool TB, int RN>
+__global__ __launch_bounds__(256) void gemm_direct_kernel(GemmArgs p, int per_inst, int ipb)
+{
+    const int t = threadIdx.x;
+    int64_t b;
+    int rem;
+    if (ipb > 0) {  // several instances per workgroup
+        const int bl = t / per_inst;
+        if (bl >= ipb)
+            return;
+        b = (int64_t)blockIdx.x * ipb + bl;
+        rem = t - bl * per_inst;
+    } else {  // one instance per blockIdx.x, its threads spread over blockIdx.y
+        b = blockIdx.x;
+        rem = (int)blockIdx.y * 256 + t;
+        if (rem >= per_inst)
+            return;
+    }
+    if (b >= p.batch)
+        return;
+    const int i = rem % p.m;
+    const int j0 = (rem / p.m) * RN;
+
+    const double *A = inst_ptr(p.A, p.Aarr, p.sA, b);
+    const double *B = inst_ptr(p.B, p.Barr, p.sB, b);
+    double *C = inst_ptr(p.C, p.Carr, p.sC, b);
+    const size_t lda = (size_t)p.lda, ldb = (size_t)p.ldb, ldc = (size_t)p.ldc;
+
+    // columns beyond n are clamped (read a valid column, result discarded)
+    int jc[RN];
+#pragma unroll
+    for (int r = 0; r < RN; ++r)
+        jc[r] = min(j0 + r, p.n - 1);
+
+    double acc[RN];
+#pragma unroll
+    for (int r = 0; r < RN; ++r)
+        acc[r] = 0.0;
+
+    for (int q = 0; q < p.k; ++q) {
+        const double a = TA ? A[(size_t)q + (size_t)i * lda] : A[(size_t)i + (size_t)q * lda];
+#pragma unroll
+        for (int r = 0; r < RN; ++r) {
+            const double bv = TB ? B[(size_t)jc[r] + (size_t)q * ldb]
+                                 : B[(size_t)q + (size_t)jc[r] * ldb];
+            acc[r] = fma(a, bv, acc[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RN; ++r) {
+        const int j = j0 + r;
+        if (j < p.n) {
+            double *c = C + (size_t)i + (size_t)j * ldc;
+            *c = (p.beta == 0.0) ? p.alpha * acc[r] : fma(p.alpha, acc[r], p.beta * (*c));
+        }
+    }
+}
+
+// C <= beta*C (alpha == 0 or k == 0); beta == 0 writes zeros without reading C.
+__global__ __launch_bounds__(256) void gemm_scale_kernel(GemmArgs p)
+{
+    const int64_t b = blockIdx.y;
+    double *C = inst_ptr(p.C, p.Carr, p.sC, b);
+    const int64_t mn = (int64_t)p.m * p.n;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < mn; e += (int64_t)gridDim.x * 256) {
+        const int j = (int)(e / p.m), i = (int)(e - (int64_t)j * p.m);
+        double *c = C + (size_t)i + (size_t)j * (size_t)p.ldc;
+        *c = (p.beta == 0.0) ? 0.0 : p.beta * (*c);
+    }
+}
+
+template <bool TA, bool TB>
+static hipError_t launch_direct_t(const GemmArgs &a, hipStream_t s)
+{
+    constexpr int RN = 4;
+    const int nb = (a.n + RN - 1) / RN;
+    const int64_t per_inst64 = (int64_t)a.m * nb;
+    if (per_inst64 > (int64_t)256 * 65535)
+        return hipErrorInvalidValue;
+    const int per_inst = (int)per_inst64;
+    if (per_inst <= 256) {
+        const int ipb = 256 / per_inst;
+        const int64_t blocks = ((int64_t)a.batch + ipb - 1) / ipb;
+        hipLaunchKernelGGL((gemm_direct_kernel<TA, TB, RN>), dim3((unsigned)blocks), dim3(256), 0,
+                           s, a, per_inst, ipb);
+    } else {
+        const int gy = (per_inst + 255) / 256;
+        hipLaunchKernelGGL((gemm_direct_kernel<TA, TB, RN>), dim3((unsigned)a.batch, gy),
+                           dim3(256), 0, s, a, per_inst, 0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_direct(bool ta, bool tb, const GemmArgs &a, hipStream_t s)
+{
+    if (!ta && !tb)
+        return launch_direct_t<false, false>(a, s);
+    if (!ta && tb)
+        return launch_direct_t<false, true>(a, s);
+    if (ta && !tb)
+        return launch_direct_t<true, false>(a, s);
+    return launch_direct_t<true, true>(a, s);
+}
+
+hipError_t launch_gemm_scale(const GemmArgs &a, hipStream_t s)
+{
+    const int64_t mn = (int64_t)a.m * a.n;
+    int64_t gx = (mn + 255) / 256;
+    if (gx > 1024)
+        gx = 1024;
+    int64_t done = 0;
+    // grid.y is limited to 65535: split very large batches into several launches
+    while (done < a.batch) {
+        const int chunk = (int)((a.batch - done) > 65535 ? 65535 : (a.batch - done));
+        GemmArgs sub = a;
+        sub.batch = chunk;
+        if (sub.Carr)
+            sub.Carr = a.Carr + done;
+        else
+            sub.C = a.C + done * a.sC;
+        hipLaunchKernelGGL(gemm_scale_kernel, dim3((unsigned)gx, chunk), dim3(256), 0, s, sub);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        done += chunk;
+    }
+    return hipSuccess;
+}
+
+}  // namespace mb

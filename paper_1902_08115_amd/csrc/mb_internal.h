@@ -1,0 +1,105 @@
+// mb_internal.h -- argument blocks, device helpers and launcher declarations
+// shared by the gfx950 kernels and the host-side C ABI of mi355blas.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mb {
+
+// One batched dgemm call, already validated.  Instance b of X is
+// Xarr[b] when Xarr != nullptr (pointer-array batch), else X + b*sX.
+struct GemmArgs {
+    int m, n, k;
+    double alpha, beta;
+    const double *A;
+    const double *const *Aarr;
+    int64_t sA;
+    int lda;
+    const double *B;
+    const double *const *Barr;
+    int64_t sB;
+    int ldb;
+    double *C;
+    double *const *Carr;
+    int64_t sC;
+    int ldc;
+    int batch;
+};
+
+// One batched lower-Cholesky call, already validated.
+struct PotrfArgs {
+    int n;
+    double *A;
+    double *const *Aarr;
+    int64_t sA;
+    int lda;
+    int *info;
+    int batch;
+};
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ const double *inst_ptr(const double *base, const double *const *arr,
+                                                  int64_t stride, int64_t b)
+{
+    return arr ? arr[b] : base + b * stride;
+}
+__device__ __forceinline__ double *inst_ptr(double *base, double *const *arr, int64_t stride,
+                                            int64_t b)
+{
+    return arr ? arr[b] : base + b * stride;
+}
+
+// FP64 matrix-core step on one wave: D(16x16) += Aop(16x4) * Bop(4x16).
+// Operand lanes: Aop[l%16][l/16] and Bop[l/16][l%16]; result register r of
+// lane l is D[4*(l/16)+r][l%16].
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Make LDS writes of this wave visible to all of its lanes (single-wave
+// groups use this instead of a workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
+template <bool WAVE_ONLY>
+__device__ __forceinline__ void group_sync()
+{
+    if constexpr (WAVE_ONLY)
+        wave_lds_sync();
+    else
+        __syncthreads();
+}
+
+// Workgroup b is dispatched to XCD b % 8; hand each XCD a contiguous range of
+// logical work ids so that tiles of one instance share an L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblk)
+{
+    constexpr int NX = 8;
+    const int per = nblk / NX;
+    if (bid >= per * NX)
+        return bid;
+    return (bid % NX) * per + bid / NX;
+}
+
+// ---- launchers (host) -------------------------------------------------------
+hipError_t launch_gemm_direct(bool ta, bool tb, const GemmArgs &a, hipStream_t s);
+hipError_t launch_gemm_packed(bool ta, bool tb, const GemmArgs &a, hipStream_t s);
+hipError_t launch_gemm_scale(const GemmArgs &a, hipStream_t s);
+hipError_t launch_potrf_lower(const PotrfArgs &a, hipStream_t s);
+hipError_t launch_fill_info(int *info, int batch, hipStream_t s);
+
+// Names of the kernel classes a call is dispatched to (profiling attribution).
+const char *packed_kernel_name(int m, int n);
+const char *potrf_kernel_name(int n);
+
+// Largest order handled by the register-resident Cholesky kernel.
+constexpr int POTRF_MAX_N = 19 * 16;
+
+}  // namespace mb

@@ -1,0 +1,138 @@
+"""C ABI of libmi355blas.so on the host (no GPU needed): every symbol the
+header declares is exported, illegal arguments return -(position) without
+launching anything, quick returns succeed, status strings and the size switch
+query behave."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mi355blas.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1902_08115_amd import _lib
+    return _lib
+
+
+def test_header_symbols_exported(L):
+    decl = set(re.findall(r"^\s*(?:int|const char \*)\s*(mb_\w+)\s*\(", open(HEADER).read(), re.M))
+    assert decl, "no declarations parsed"
+    assert decl == set(L.EXPORTS), decl ^ set(L.EXPORTS)
+    for name in decl:
+        assert hasattr(L.lib, name), name
+
+
+def test_version_and_status(L):
+    assert L.version() >= 100
+    assert L.status_string(0) == "success"
+    assert "HIP" in L.status_string(L.MB_ERR_HIP)
+    assert "unsupported" in L.status_string(L.MB_ERR_UNSUPPORTED)
+
+
+P = 0x1000  # a non-null placeholder address: illegal calls never dereference it
+
+
+def test_dgemm_argument_errors(L):
+    g = lambda *a: L.dgemm(*a)  # noqa: E731
+    ok = ("N", "N", 4, 4, 4, 1.0, P, 4, P, 4, 1.0, P, 4)
+    assert g("X", *ok[1:]) == -1
+    assert g("N", "q", *ok[2:]) == -2
+    assert g("N", "N", -1, *ok[3:]) == -3
+    assert g("N", "N", 4, -1, *ok[4:]) == -4
+    assert g("N", "N", 4, 4, -1, *ok[5:]) == -5
+    assert g("N", "N", 4, 4, 4, 1.0, P, 3, P, 4, 1.0, P, 4) == -8       # lda < m
+    assert g("T", "N", 4, 4, 6, 1.0, P, 4, P, 6, 1.0, P, 4) == -8       # lda < k for 'T'
+    assert g("N", "N", 4, 4, 6, 1.0, P, 4, P, 5, 1.0, P, 4) == -10      # ldb < k
+    assert g("N", "t", 4, 5, 6, 1.0, P, 4, P, 4, 1.0, P, 4) == -10      # ldb < n for 'T'
+    assert g("N", "N", 4, 4, 4, 1.0, P, 4, P, 4, 1.0, P, 3) == -13      # ldc < m
+    assert g("N", "N", 0, 4, 4, 1.0, P, 0, P, 4, 1.0, P, 1) == -8       # lda >= 1 even if m == 0
+    assert g("N", "N", 4, 4, 4, 1.0, None, 4, P, 4, 1.0, P, 4) == -7    # null A with work
+    assert g("N", "N", 4, 4, 4, 1.0, P, 4, None, 4, 1.0, P, 4) == -9
+    assert g("N", "N", 4, 4, 4, 1.0, P, 4, P, 4, 1.0, None, 4) == -12
+
+
+def test_dgemm_quick_returns_without_gpu(L):
+    # nothing is launched for these, so they succeed on a host without a GPU
+    assert L.dgemm("N", "N", 0, 4, 4, 1.0, None, 1, None, 4, 1.0, None, 1) == 0
+    assert L.dgemm("N", "N", 4, 0, 4, 1.0, None, 4, None, 4, 1.0, None, 4) == 0
+    assert L.dgemm("N", "N", 4, 4, 4, 0.0, None, 4, None, 4, 1.0, P, 4) == 0
+    assert L.dgemm("n", "c", 4, 4, 0, 2.0, None, 4, None, 4, 1.0, P, 4) == 0
+    assert L.dgemm_strided_batched("T", "T", 4, 4, 4, 1.0, None, 4, 16, None, 4, 16, 1.0, None, 4,
+                                   16, 0) == 0
+
+
+def test_dgemm_strided_argument_errors(L):
+    f = L.dgemm_strided_batched
+    base = dict(ta="N", tb="N", m=4, n=4, k=4, al=1.0, A=P, lda=4, sA=16, B=P, ldb=4, sB=16,
+                be=1.0, C=P, ldc=4, sC=16, batch=2)
+
+    def call(**kw):
+        a = {**base, **kw}
+        return f(a["ta"], a["tb"], a["m"], a["n"], a["k"], a["al"], a["A"], a["lda"], a["sA"],
+                 a["B"], a["ldb"], a["sB"], a["be"], a["C"], a["ldc"], a["sC"], a["batch"])
+    assert call(ta="x") == -1 and call(tb="x") == -2
+    assert call(m=-2) == -3 and call(n=-2) == -4 and call(k=-2) == -5
+    assert call(lda=3) == -8 and call(ldb=3) == -11 and call(ldc=3) == -15
+    assert call(sA=-1) == -9 and call(sB=-1) == -12 and call(sC=-1) == -16
+    assert call(batch=-1) == -17
+    assert call(sC=15) == -16  # instances of C would overlap
+    assert call(A=None) == -7 and call(B=None) == -10 and call(C=None) == -14
+    g = L.lib.mb_dgemm_strided_batched_ex
+    assert g(b"N", b"N", 4, 4, 4, 1.0, P, 4, 16, P, 4, 16, 1.0, P, 4, 16, 2, 7, None) == -18
+
+
+def test_dgemm_pointer_array_argument_errors(L):
+    f = L.dgemm_batched
+    assert f("N", "N", 4, 4, 4, 1.0, P, 4, P, 4, 1.0, P, 4, -1) == -14
+    assert f("N", "N", 4, 4, 4, 1.0, P, 3, P, 4, 1.0, P, 4, 2) == -8
+    assert f("N", "N", 4, 4, 4, 1.0, P, 4, P, 3, 1.0, P, 4, 2) == -10
+    assert f("N", "N", 4, 4, 4, 1.0, P, 4, P, 4, 1.0, P, 2, 2) == -13
+    assert f("N", "N", 4, 4, 4, 1.0, None, 4, P, 4, 1.0, P, 4, 2) == -7
+    assert f("N", "N", 4, 4, 4, 1.0, P, 4, None, 4, 1.0, P, 4, 2) == -9
+    assert f("N", "N", 4, 4, 4, 1.0, P, 4, P, 4, 1.0, None, 4, 2) == -12
+    g = L.lib.mb_dgemm_batched_ex
+    assert g(b"N", b"N", 4, 4, 4, 1.0, P, 4, P, 4, 1.0, P, 4, 2, -1, None) == -15
+
+
+def test_dpotrf_argument_errors(L):
+    assert L.dpotrf("X", 4, P, 4, P) == -1
+    assert L.dpotrf("U", 4, P, 4, P) == L.MB_ERR_UNSUPPORTED
+    assert L.dpotrf("L", -1, P, 4, P) == -2
+    assert L.dpotrf("L", 4, P, 3, P) == -4
+    assert L.dpotrf("L", 4, None, 4, P) == -3
+    assert L.dpotrf("L", 4, P, 4, None) == -5
+    assert L.dpotrf("l", 305, P, 305, P) == L.MB_ERR_UNSUPPORTED
+    f = L.dpotrf_strided_batched
+    assert f("L", 4, P, 4, -1, P, 2) == -5
+    assert f("L", 4, P, 4, 15, P, 2) == -5  # overlapping instances
+    assert f("L", 4, P, 4, 16, P, -1) == -7
+    assert f("L", 4, P, 4, 16, None, 2) == -6
+    assert f("L", 4, P, 4, 16, P, 0) == 0   # batch == 0: quick return
+    g = L.dpotrf_batched
+    assert g("L", 4, P, 4, P, -1) == -6
+    assert g("L", 4, None, 4, P, 2) == -3
+    assert g("L", 4, P, 4, None, 2) == -5
+    assert g("L", 4, P, 2, P, 2) == -4
+
+
+def test_size_switch_query(L):
+    assert L.dgemm_select("N", "N", 4, 4, 4) == L.VARIANT_DIRECT
+    assert L.dgemm_select("t", "c", 300, 300, 300) == L.VARIANT_PACKED
+    assert L.dgemm_select("x", "N", 4, 4, 4) == -1
+    # the choice depends on the shape only
+    for ta in "NT":
+        for tb in "NT":
+            assert L.dgemm_select(ta, tb, 128, 128, 128) == L.VARIANT_PACKED
+
+
+def test_kernel_name_queries(L):
+    assert L.dgemm_kernel_name("N", "N", 4, 4, 4) == "gemm_direct"
+    assert L.dgemm_kernel_name("N", "N", 4, 4, 4, L.VARIANT_PACKED).startswith("gemm_packed")
+    assert L.dgemm_kernel_name("T", "T", 256, 256, 256).startswith("gemm_packed")
+    assert L.dgemm_kernel_name("N", "N", 4, 4, 0) == "gemm_scale"
+    assert L.dgemm_kernel_name("x", "N", 4, 4, 4) == "illegal"
+    assert L.dpotrf_kernel_name(256) == "potrf_nt16"
+    assert L.dpotrf_kernel_name(400) == "unsupported"

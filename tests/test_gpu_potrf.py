@@ -1,0 +1,186 @@
+"""GPU parity of the batched lower Cholesky (dpotrf 'L') against the CPU oracle,
+through the C ABI: info bit-exact, the reconstruction residual and the factor
+within 1e-12, exact integer factors bit for bit, untouched upper triangle."""
+import numpy as np
+import pytest
+
+from paper_1902_08115_amd import inputs
+from tests.gpu_util import POTRF_TOL, dev, host, potrf_check, say, torch_mods
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(n, A, batch, lda=None):
+    torch, _lib, _ = torch_mods()
+    lda = A.shape[2] if lda is None else lda
+    dA = dev(A)
+    info = torch.full((max(batch, 1),), -7, dtype=torch.int32, device="cuda")
+    st = _lib.dpotrf_strided_batched("L", n, dA.data_ptr(), lda, A.shape[1] * A.shape[2],
+                                     info.data_ptr(), batch, torch.cuda.current_stream().cuda_stream)
+    assert st == 0, st
+    return host(dA).reshape(A.shape), host(info)[:batch]
+
+
+@pytest.mark.parametrize("si,n", list(enumerate(inputs.POTRF_SWEEP_SIZES)))
+def test_sweep_sizes_with_failing_instance(si, n):
+    """SPD A = M M^T + nI at every sweep size, one instance with a_jj = -1:
+    info bit-exact, residual and factor within 1e-12, upper triangle (NaN
+    sentinels) and ld padding untouched."""
+    g = inputs.rng(inputs.seed_for(2, si))
+    batch = 24 if n <= 128 else 8
+    A = inputs.spd_batch(g, batch, n, ld=n + 3, upper_value=np.nan)
+    b_bad, j_bad = inputs.make_non_spd(g, A, n)
+    say(f"dpotrf sweep n={n} batch={batch} bad=({b_bad},{j_bad})")
+    Ag, info = _run(n, A, batch)
+    res, lerr, info_ref, _ = potrf_check(Ag, A, n, n + 3)
+    exp = np.zeros(batch, dtype=np.int32)
+    exp[b_bad] = j_bad + 1
+    assert np.array_equal(info, exp) and np.array_equal(info_ref, exp), (info, info_ref)
+    assert res <= POTRF_TOL and lerr <= POTRF_TOL, (res, lerr)
+    iu = np.triu_indices(n, 1)
+    for b in range(batch):
+        M = Ag[b].T
+        assert np.isnan(M[:n, :n][iu]).all(), "strict upper triangle touched"
+        assert np.isnan(M[n:, :n]).all(), "ld padding touched"
+    # the failing instance: columns before the failing one hold the valid factor
+    if j_bad > 0:
+        Lr = np.ascontiguousarray(A[b_bad:b_bad + 1]).ravel().copy()
+        import oracle
+        assert oracle.dpotrf_l_raw(n, Lr, n + 3) == j_bad + 1
+        Lr = Lr.reshape(A[b_bad:b_bad + 1].shape)[0].T[:n, :j_bad]
+        Lg = Ag[b_bad].T[:n, :j_bad]
+        low = np.tril(np.ones((n, j_bad), dtype=bool))
+        d = np.linalg.norm((Lg - Lr)[low]) / np.linalg.norm(Lr[low])
+        assert d <= POTRF_TOL, d
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 15, 16, 17, 31, 33, 47, 64, 65, 100, 129, 200, 256, 300])
+def test_exact_integer_factor(n):
+    """A = L0 L0^T with integer L0 (diagonal in {1,2,4}): the factor is L0
+    exactly for any evaluation order, so the GPU result must match bit for bit."""
+    g = inputs.rng(8000 + n)
+    batch = 3
+    A = np.full((batch, n, n + 1), np.nan)
+    L0s = []
+    for b in range(batch):
+        L0 = np.tril(g.integers(-3, 4, size=(n, n)), -1) + np.diag(g.choice([1, 2, 4], size=n))
+        L0s.append(L0.astype(np.float64))
+        S = (L0 @ L0.T).astype(np.float64)
+        A[b, :, :n] = S.T  # column-major: A[b, j, i] = S[i, j]
+    say(f"dpotrf exact n={n}")
+    Ag, info = _run(n, A, batch)
+    assert (info == 0).all()
+    for b in range(batch):
+        assert np.array_equal(np.tril(Ag[b].T[:n, :n]), L0s[b]), f"instance {b}"
+
+
+def test_info_closed_form_every_column():
+    """a_jj = -1 in instance j (j = 0..n-1) gives info = j+1 in every instance."""
+    n = 40
+    g = inputs.rng(8100)
+    A = inputs.spd_batch(g, n, n)
+    for j in range(n):
+        A[j, j, j] = -1.0
+    say("dpotrf info every column n=40")
+    _, info = _run(n, A, n)
+    assert np.array_equal(info, np.arange(1, n + 1, dtype=np.int32))
+
+
+def test_nan_and_zero_pivots():
+    n = 20
+    g = inputs.rng(8200)
+    A = inputs.spd_batch(g, 4, n)
+    A[0, 3, 3] = np.nan
+    A[1, 0, 0] = 0.0
+    A[2, n - 1, n - 1] = -0.0
+    say("dpotrf nan/zero pivots")
+    _, info = _run(n, A, 4)
+    # NaN pivot -> 4, zero pivot -> 1, a -0.0 diagonal at the end gives a
+    # pivot -0.0 - sum l^2 <= 0 -> n; the last instance is SPD
+    assert list(info) == [4, 1, n, 0], info
+    Xr = np.ascontiguousarray(A).ravel().copy()
+    import oracle
+    ref = oracle.dpotrf_l_strided_batched(n, Xr, n, n * n, 4)
+    assert np.array_equal(info, ref)
+
+
+def test_pointer_array_equals_strided():
+    torch, _lib, _ = torch_mods()
+    for n in (12, 48, 160):
+        g = inputs.rng(8300 + n)
+        batch = 5
+        A = inputs.spd_batch(g, batch, n, ld=n + 2)
+        say(f"dpotrf pointer-array n={n}")
+        As, infs = _run(n, A, batch)
+        dA = dev(A)
+        ptr = torch.tensor([dA.data_ptr() + 8 * b * A.shape[1] * A.shape[2] for b in range(batch)],
+                           dtype=torch.int64, device="cuda")
+        info = torch.full((batch,), -7, dtype=torch.int32, device="cuda")
+        st = _lib.dpotrf_batched("L", n, ptr.data_ptr(), n + 2, info.data_ptr(), batch,
+                                 torch.cuda.current_stream().cuda_stream)
+        assert st == 0
+        assert np.array_equal(host(dA).reshape(A.shape), As, equal_nan=True)
+        assert np.array_equal(host(info), infs)
+
+
+def test_single_call_and_trivial_sizes():
+    torch, _lib, _ = torch_mods()
+    s = torch.cuda.current_stream().cuda_stream
+    g = inputs.rng(8400)
+    A = inputs.spd_batch(g, 1, 37)
+    dA = dev(A)
+    info = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    say("dpotrf single n=37")
+    assert _lib.dpotrf("L", 37, dA.data_ptr(), 37, info.data_ptr(), s) == 0
+    Ag = host(dA).reshape(A.shape)
+    res, lerr, _, _ = potrf_check(Ag, A, 37, 37)
+    assert int(host(info)[0]) == 0 and res <= POTRF_TOL and lerr <= POTRF_TOL
+    # n == 0: info set to 0 for every instance, nothing else touched
+    info = torch.full((6,), -7, dtype=torch.int32, device="cuda")
+    say("dpotrf n=0")
+    assert _lib.dpotrf_strided_batched("L", 0, 0, 1, 0, info.data_ptr(), 6, s) == 0
+    assert (host(info) == 0).all()
+    # batch == 0: nothing launched
+    info = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    assert _lib.dpotrf_strided_batched("L", 5, 0, 5, 25, info.data_ptr(), 0, s) == 0
+    assert int(host(info)[0]) == -7
+
+
+def test_full_batch_sampled():
+    """The sweep at its full batch of 4096 (inputs generated on the device),
+    every instance's info checked, sampled instances against the oracle."""
+    torch, _lib, blas = torch_mods()
+    import oracle
+    s = torch.cuda.current_stream().cuda_stream
+    for si, n in enumerate(inputs.POTRF_SWEEP_SIZES):
+        batch = inputs.POTRF_SWEEP_BATCH
+        A = inputs.torch_spd(batch, n, seed=inputs.seed_for(2, si))
+        rs = np.random.Generator(np.random.PCG64(inputs.seed_for(2, si)))
+        bad_b, bad_j = int(rs.integers(0, batch)), int(rs.integers(0, n))
+        A[bad_b, bad_j, bad_j] = -1.0
+        idx = sorted({0, batch - 1, bad_b, *rs.integers(0, batch, size=4).tolist()})
+        sel = torch.tensor(idx, device="cuda")
+        A0 = A[sel].contiguous().cpu().numpy()
+        info = torch.full((batch,), -7, dtype=torch.int32, device="cuda")
+        say(f"dpotrf full batch n={n}")
+        st = _lib.dpotrf_strided_batched("L", n, A.data_ptr(), n, n * n, info.data_ptr(), batch, s)
+        assert st == 0
+        inf = host(info)
+        exp = np.zeros(batch, dtype=np.int32)
+        exp[bad_b] = bad_j + 1
+        assert np.array_equal(inf, exp)
+        Ag = A[sel].contiguous().cpu().numpy()
+        for j, b in enumerate(idx):
+            if b == bad_b:
+                continue
+            X = np.asfortranarray(A0[j].copy())
+            assert oracle.dpotrf_l(X) == 0
+            Lr = np.tril(X)
+            Lg = np.tril(Ag[j])
+            assert np.linalg.norm(Lg - Lr) / np.linalg.norm(Lr) <= POTRF_TOL
+            Al = A0[j].astype(np.longdouble)
+            Ll = Lg.astype(np.longdouble)
+            res = np.sqrt(((Al - Ll @ Ll.T) ** 2).sum() / (Al ** 2).sum())
+            assert float(res) <= POTRF_TOL
+        del A
+        torch.cuda.empty_cache()
