@@ -236,9 +236,9 @@ def parity_spot_check(torch, _lib, oracle, gemm, potrf, stream):
             r = np.sqrt(((a0 - lg @ lg.T) ** 2).sum() / (a0 ** 2).sum())
             worst_res = max(worst_res, float(r))
         del X
-    return {"dgemm_max_rel_err": worst_gemm, "dpotrf_max_residual": worst_res,
+    return {"dgemm_max_rel_err": float(worst_gemm), "dpotrf_max_residual": float(worst_res),
             "dpotrf_info_exact": info_ok, "tolerance": 1e-12,
-            "pass": worst_gemm <= 1e-12 and worst_res <= 1e-12 and info_ok}
+            "pass": bool(worst_gemm <= 1e-12 and worst_res <= 1e-12 and info_ok)}
 
 
 def crossover(torch, _lib, inputs, args):

@@ -213,7 +213,7 @@ __global__ __launch_bounds__(WM *WN *IPB * 64) void gemm_packed_kernel(GemmArgs 
         for (int tj = 0; tj < TN; ++tj) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int gj = j0 + (wn * TN + tj) * 16 + 4 * lg + r;
+                const int gj = j0 + (wn * TN + tj) * 16 + lg + 4 * r;
                 if (gi < m && gj < n) {
                     double *c = C + (size_t)gi + (size_t)gj * ldc;
                     const double v = acc[ti][tj][r];

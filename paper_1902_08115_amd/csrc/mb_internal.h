@@ -53,7 +53,7 @@ __device__ __forceinline__ double *inst_ptr(double *base, double *const *arr, in
 
 // FP64 matrix-core step on one wave: D(16x16) += Aop(16x4) * Bop(4x16).
 // Operand lanes: Aop[l%16][l/16] and Bop[l/16][l%16]; result register r of
-// lane l is D[4*(l/16)+r][l%16].
+// lane l is D[l/16 + 4*r][l%16] (rows interleaved across the registers).
 __device__ __forceinline__ d4 mfma16(double a, double b, d4 c)
 {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);

@@ -39,7 +39,7 @@ struct PotrfSmem {
 };
 
 // Factor one 16x16 diagonal tile held in accumulator order -- lane (g, i),
-// register r holds T[i][4g + r] -- by one whole wave (inner_edge_dpotrf).
+// register r holds T[i][g + 4r] -- by one whole wave (inner_edge_dpotrf).
 // Column c is eliminated in step c: its current values are published through
 // LDS, every lane forms l_ic = T[i][c]/l_cc for its row and l_qc for its four
 // columns q, and updates its own entries T[i][q] -= l_ic*l_qc (c < q <= i).
@@ -57,26 +57,26 @@ __device__ __forceinline__ void factor_diag_tile(d4 &t, d4 &x, Smem &S, int J, i
     const int i = lane & 15, g = lane >> 4;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-        x[r] = (i == 4 * g + r) ? 1.0 : 0.0;
+        x[r] = (i == g + 4 * r) ? 1.0 : 0.0;
     bool failed = false;
     double lic_prev = 0.0;  // l_{i,c-1} of the previous step
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
         const int buf = c & 1;
         // publish column c of T and (from step 1 on) the scaled row c-1 of X
-        if (g == (c >> 2))
-            S.col[buf][i] = t[c & 3];
+        if (g == (c & 3))
+            S.col[buf][i] = t[c >> 2];
         if (c > 0 && i == c - 1) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                S.xrow[buf][4 * g + r] = x[r];
+                S.xrow[buf][g + 4 * r] = x[r];
         }
         wave_lds_sync();
         // X update of step c-1: rows i > c-1 lose l_{i,c-1} * (scaled row c-1)
         if (c > 0 && i > c - 1) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                x[r] = fma(-lic_prev, S.xrow[buf][4 * g + r], x[r]);
+                x[r] = fma(-lic_prev, S.xrow[buf][g + 4 * r], x[r]);
         }
         const double piv = S.col[buf][c];
         if (!failed && !(piv > 0.0)) {
@@ -99,12 +99,12 @@ __device__ __forceinline__ void factor_diag_tile(d4 &t, d4 &x, Smem &S, int J, i
             lic = 0.0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int q = 4 * g + r;
+            const int q = g + 4 * r;
             if (q > c && q <= i && !failed)
                 t[r] = fma(-lic, S.col[buf][q] * rinv, t[r]);
         }
-        if (g == (c >> 2))
-            t[c & 3] = (i >= c) ? lic : 0.0;
+        if (g == (c & 3))
+            t[c >> 2] = (i >= c) ? lic : 0.0;
         if (i == c) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
@@ -115,7 +115,7 @@ __device__ __forceinline__ void factor_diag_tile(d4 &t, d4 &x, Smem &S, int J, i
     // zero the strict upper part of L (entries of T never touched above)
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-        if (4 * g + r > i)
+        if (g + 4 * r > i)
             t[r] = 0.0;
 }
 
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(NW *IPB * 64) void potrf_lower_kernel(PotrfArgs p)
     }
 
     // load the owned tiles in accumulator order: lane (lg, lr), reg r holds
-    // element (16I + lr, 16K + 4lg + r); identity outside the n x n matrix and
+    // element (16I + lr, 16K + lg + 4r); identity outside the n x n matrix and
     // zeros in the strict upper part of diagonal tiles.
     d4 acc[SLOTS];
 #pragma unroll
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(NW *IPB * 64) void potrf_lower_kernel(PotrfArgs p)
         for (int r = 0; r < 4; ++r) {
             double v = 0.0;
             if (tI[s] >= 0) {
-                const int gi = 16 * tI[s] + lr, gc = 16 * tK[s] + 4 * lg + r;
+                const int gi = 16 * tI[s] + lr, gc = 16 * tK[s] + lg + 4 * r;
                 if (gi < n && gc < n) {
                     if (gi >= gc)
                         v = A[(size_t)gi + (size_t)gc * lda];
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(NW *IPB * 64) void potrf_lower_kernel(PotrfArgs p)
                 const int gi = 16 * J + lr;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int gc = 16 * J + 4 * lg + r;
+                    const int gc = 16 * J + lg + 4 * r;
                     if (gi < n && gc <= gi && gc < fail_col)
                         A[(size_t)gi + (size_t)gc * lda] = t[r];
                 }
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(NW *IPB * 64) void potrf_lower_kernel(PotrfArgs p)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     S.P[pb][tI[s]][r][lane] = x[r];
-                    const int gc = 16 * J + 4 * lg + r;
+                    const int gc = 16 * J + lg + 4 * r;
                     if (gi < n && gc < n && gc < fail_col)
                         A[(size_t)gi + (size_t)gc * lda] = x[r];
                 }
