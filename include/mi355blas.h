@@ -121,12 +121,25 @@ int mb_dgemm_batched_ex(char transa, char transb, int m, int n, int k, double al
                         int ldb, double beta, double *const *Carray, int ldc, int batch,
                         int variant, hipStream_t stream);
 
+/* Tuning entry: the strided batch on one forced configuration of the packed
+ * kernel menu, 0 <= config < mb_dgemm_config_count() (position 18; returns
+ * MB_ERR_UNSUPPORTED when a one-wave-per-instance configuration cannot hold
+ * the m x n result).  The autotuner measures the menu with it. */
+int mb_dgemm_strided_batched_config(char transa, char transb, int m, int n, int k,
+                                    double alpha, const double *A, int lda, int64_t strideA,
+                                    const double *B, int ldb, int64_t strideB, double beta,
+                                    double *C, int ldc, int64_t strideC, int batch, int config,
+                                    hipStream_t stream);
+int mb_dgemm_config_count(void);
+/* Static name of a packed configuration ("illegal" when out of range). */
+const char *mb_dgemm_config_name(int config);
+
 /* Host-only query: the kernel family (MB_VARIANT_DIRECT or MB_VARIANT_PACKED)
  * that the plain calls select for this shape, or -1 for an illegal trans. */
 int mb_dgemm_select(char transa, char transb, int m, int n, int k);
 
 /* Host-only query: a static name of the kernel class the call would run
- * ("gemm_direct", "gemm_packed_tile64", ...), for attributing profiles; the
+ * ("gemm_direct", "gemm_packed_tile64_k16", ...), for attributing profiles; the
  * scalar alpha/beta quick returns are not considered. */
 const char *mb_dgemm_kernel_name(char transa, char transb, int m, int n, int k, int variant);
 

@@ -20,14 +20,16 @@ VARIANT_AUTO, VARIANT_DIRECT, VARIANT_PACKED = 0, 1, 2
 # every symbol the header declares, in declaration order
 EXPORTS = (
     "mb_dgemm", "mb_dgemm_strided_batched", "mb_dgemm_batched",
-    "mb_dgemm_strided_batched_ex", "mb_dgemm_batched_ex", "mb_dgemm_select",
+    "mb_dgemm_strided_batched_ex", "mb_dgemm_batched_ex", "mb_dgemm_strided_batched_config",
+    "mb_dgemm_config_count", "mb_dgemm_config_name", "mb_dgemm_select",
     "mb_dgemm_kernel_name", "mb_dpotrf", "mb_dpotrf_strided_batched", "mb_dpotrf_batched",
     "mb_dpotrf_kernel_name",
     "mb_status_string", "mb_version",
 )
 
 
-_STRING_FNS = ("mb_status_string", "mb_dgemm_kernel_name", "mb_dpotrf_kernel_name")
+_STRING_FNS = ("mb_status_string", "mb_dgemm_kernel_name", "mb_dpotrf_kernel_name",
+               "mb_dgemm_config_name")
 
 
 class MbError(RuntimeError):
@@ -57,6 +59,9 @@ def _load():
     lib.mb_dgemm_batched.argtypes = [c_char, c_char, c_int, c_int, c_int, c_double, vp, c_int,
                                      vp, c_int, c_double, vp, c_int, c_int, vp]
     lib.mb_dgemm_batched_ex.argtypes = lib.mb_dgemm_batched.argtypes[:-1] + [c_int, vp]
+    lib.mb_dgemm_strided_batched_config.argtypes = lib.mb_dgemm_strided_batched_ex.argtypes
+    lib.mb_dgemm_config_count.argtypes = []
+    lib.mb_dgemm_config_name.argtypes = [c_int]
     lib.mb_dgemm_select.argtypes = [c_char, c_char, c_int, c_int, c_int]
     lib.mb_dpotrf.argtypes = [c_char, c_int, vp, c_int, vp, vp]
     lib.mb_dpotrf_strided_batched.argtypes = [c_char, c_int, vp, c_int, c_i64, vp, c_int, vp]
@@ -104,6 +109,21 @@ def dgemm_batched(transa, transb, m, n, k, alpha, Aarr, lda, Barr, ldb, beta, Ca
                                     Barr, ldb, float(beta), Carr, ldc, batch, stream)
     return lib.mb_dgemm_batched_ex(_ch(transa), _ch(transb), m, n, k, float(alpha), Aarr, lda,
                                    Barr, ldb, float(beta), Carr, ldc, batch, int(variant), stream)
+
+
+def dgemm_strided_batched_config(transa, transb, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C,
+                                 ldc, sC, batch, config, stream=0) -> int:
+    return lib.mb_dgemm_strided_batched_config(_ch(transa), _ch(transb), m, n, k, float(alpha), A,
+                                               lda, sA, B, ldb, sB, float(beta), C, ldc, sC,
+                                               batch, int(config), stream)
+
+
+def dgemm_config_count() -> int:
+    return lib.mb_dgemm_config_count()
+
+
+def dgemm_config_name(config) -> str:
+    return lib.mb_dgemm_config_name(int(config)).decode()
 
 
 def dgemm_select(transa, transb, m, n, k) -> int:

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "../../include/mi355blas.h"
+#include "gemm_tuned.h"
 #include "mb_internal.h"
 
 namespace {
@@ -23,17 +24,53 @@ int trans_code(char t)  // 0 = N, 1 = T, -1 = illegal
     }
 }
 
-// Switching point between the direct and the packed kernel families, per
-// trans case (index 2*ta + tb): the direct kernel is used while
-// max(m, n, k) <= the value.  Measured on MI355X with the square sweep of the
-// benchmark (see the dgemm crossover profile).
-constexpr int kCrossover[4] = {8, 8, 8, 8};
+// Size-class dispatch from the measured table (gemm_tuned.h): the switch
+// between the direct and the packed family and the packed tile configuration
+// depend on the trans case and max(m, n, k) only -- never on the batch -- so a
+// batch computes every instance exactly as the single call does.
+struct Choice {
+    int variant, config;
+};
 
-int select_variant(int ta, int tb, int m, int n, int k)
+int size_class(int m, int n, int k)
 {
     int mx = m > n ? m : n;
     mx = mx > k ? mx : k;
-    return mx <= kCrossover[2 * ta + tb] ? MB_VARIANT_DIRECT : MB_VARIANT_PACKED;
+    int e = 0;
+    while (e < mb::kGemmTuneEntries - 1 && mx > mb::kGemmTuneMaxDim[e])
+        ++e;
+    return e;
+}
+
+// A WAVE configuration holds a whole instance: fall back to the first TILE
+// configuration when the instance does not fit (non-square shapes).
+int fit_config(int config, int m, int n)
+{
+    const int lim = mb::packed_config_wave_limit(config);
+    if (lim > 0 && (m > lim || n > lim))
+        return 3;  // tile64_k16
+    return config;
+}
+
+Choice select(int ta, int tb, int m, int n, int k, int variant)
+{
+    const int e = size_class(m, n, k);
+    const int *t = mb::kGemmTune[2 * ta + tb][e];
+    Choice c;
+    c.variant = (variant == MB_VARIANT_AUTO) ? t[0] : variant;
+    int cfg = t[1];
+    if (c.variant == MB_VARIANT_PACKED && cfg < 0) {
+        // the table picks the direct family here: use the smallest packed shape that fits
+        const int mx = m > n ? m : n;
+        cfg = mx <= 16 ? 0 : (mx <= 32 ? 1 : 3);
+    }
+    c.config = (c.variant == MB_VARIANT_PACKED) ? fit_config(cfg, m, n) : -1;
+    return c;
+}
+
+int select_variant(int ta, int tb, int m, int n, int k)
+{
+    return select(ta, tb, m, n, k, MB_VARIANT_AUTO).variant;
 }
 
 int to_status(hipError_t e) { return e == hipSuccess ? MB_OK : MB_ERR_HIP; }
@@ -56,7 +93,8 @@ int check_gemm(char transa, char transb, int m, int n, int k, int lda, int ldb, 
     return MB_OK;
 }
 
-int run_gemm(int ta, int tb, GemmArgs &a, int variant, hipStream_t s)
+// variant: MB_VARIANT_*; config >= 0 forces a packed configuration.
+int run_gemm(int ta, int tb, GemmArgs &a, int variant, int config, hipStream_t s)
 {
     if (a.m == 0 || a.n == 0 || a.batch == 0)
         return MB_OK;
@@ -64,17 +102,18 @@ int run_gemm(int ta, int tb, GemmArgs &a, int variant, hipStream_t s)
         return MB_OK;
     if (a.alpha == 0.0 || a.k == 0)
         return to_status(mb::launch_gemm_scale(a, s));
-    if (variant == MB_VARIANT_AUTO)
-        variant = select_variant(ta, tb, a.m, a.n, a.k);
-    if (variant == MB_VARIANT_DIRECT)
+    if (config >= 0)
+        return to_status(mb::launch_gemm_packed_config(config, ta, tb, a, s));
+    const Choice c = select(ta, tb, a.m, a.n, a.k, variant);
+    if (c.variant == MB_VARIANT_DIRECT)
         return to_status(mb::launch_gemm_direct(ta, tb, a, s));
-    return to_status(mb::launch_gemm_packed(ta, tb, a, s));
+    return to_status(mb::launch_gemm_packed_config(c.config, ta, tb, a, s));
 }
 
 int gemm_strided(char transa, char transb, int m, int n, int k, double alpha, const double *A,
                  int lda, int64_t strideA, const double *B, int ldb, int64_t strideB, double beta,
                  double *C, int ldc, int64_t strideC, int batch, int variant, int pos_variant,
-                 hipStream_t stream)
+                 hipStream_t stream, int config = -1)
 {
     int st = check_gemm(transa, transb, m, n, k, lda, ldb, ldc, 8, 11, 15);
     if (st != MB_OK)
@@ -98,7 +137,7 @@ int gemm_strided(char transa, char transb, int m, int n, int k, double alpha, co
     a.B = B; a.sB = strideB; a.ldb = ldb;
     a.C = C; a.sC = strideC; a.ldc = ldc;
     a.batch = batch;
-    return run_gemm(trans_code(transa), trans_code(transb), a, variant, stream);
+    return run_gemm(trans_code(transa), trans_code(transb), a, variant, config, stream);
 }
 
 int gemm_array(char transa, char transb, int m, int n, int k, double alpha,
@@ -124,7 +163,7 @@ int gemm_array(char transa, char transb, int m, int n, int k, double alpha,
     a.Barr = Barray; a.ldb = ldb;
     a.Carr = Carray; a.ldc = ldc;
     a.batch = batch;
-    return run_gemm(trans_code(transa), trans_code(transb), a, variant, stream);
+    return run_gemm(trans_code(transa), trans_code(transb), a, variant, -1, stream);
 }
 
 int uplo_check(char uplo)  // 0 lower, 1 upper (unsupported), -1 illegal
@@ -167,7 +206,7 @@ int mb_dgemm(char transa, char transb, int m, int n, int k, double alpha, const 
     a.m = m; a.n = n; a.k = k; a.alpha = alpha; a.beta = beta;
     a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.C = C; a.ldc = ldc;
     a.batch = 1;
-    return run_gemm(trans_code(transa), trans_code(transb), a, MB_VARIANT_AUTO, stream);
+    return run_gemm(trans_code(transa), trans_code(transb), a, MB_VARIANT_AUTO, -1, stream);
 }
 
 int mb_dgemm_strided_batched(char transa, char transb, int m, int n, int k, double alpha,
@@ -187,6 +226,25 @@ int mb_dgemm_strided_batched_ex(char transa, char transb, int m, int n, int k, d
     return gemm_strided(transa, transb, m, n, k, alpha, A, lda, strideA, B, ldb, strideB, beta,
                         C, ldc, strideC, batch, variant, 18, stream);
 }
+
+int mb_dgemm_strided_batched_config(char transa, char transb, int m, int n, int k,
+                                    double alpha, const double *A, int lda, int64_t strideA,
+                                    const double *B, int ldb, int64_t strideB, double beta,
+                                    double *C, int ldc, int64_t strideC, int batch, int config,
+                                    hipStream_t stream)
+{
+    if (config < 0 || config >= mb::packed_config_count())
+        return -18;
+    const int lim = mb::packed_config_wave_limit(config);
+    if (lim > 0 && (m > lim || n > lim))
+        return MB_ERR_UNSUPPORTED;
+    return gemm_strided(transa, transb, m, n, k, alpha, A, lda, strideA, B, ldb, strideB, beta,
+                        C, ldc, strideC, batch, MB_VARIANT_PACKED, 18, stream, config);
+}
+
+int mb_dgemm_config_count(void) { return mb::packed_config_count(); }
+
+const char *mb_dgemm_config_name(int config) { return mb::packed_config_name(config); }
 
 int mb_dgemm_batched(char transa, char transb, int m, int n, int k, double alpha,
                      const double *const *Aarray, int lda, const double *const *Barray, int ldb,
@@ -222,11 +280,10 @@ const char *mb_dgemm_kernel_name(char transa, char transb, int m, int n, int k, 
         return "none";
     if (k == 0)
         return "gemm_scale";
-    if (variant == MB_VARIANT_AUTO)
-        variant = select_variant(ta, tb, m, n, k);
-    if (variant == MB_VARIANT_DIRECT)
+    const Choice c = select(ta, tb, m, n, k, variant);
+    if (c.variant == MB_VARIANT_DIRECT)
         return "gemm_direct";
-    return mb::packed_kernel_name(m, n);
+    return mb::packed_config_name(c.config);
 }
 
 const char *mb_dpotrf_kernel_name(int n)

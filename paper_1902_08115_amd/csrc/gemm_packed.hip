@@ -3,133 +3,133 @@
 // The analogue of the paper's algorithmic variants 'C'/'B' (Sec. 2.2, Table 1):
 // the factors are packed, k-panel by k-panel, into an on-chip buffer whose
 // layout suits the compute kernel, transposing while packing so that every
-// trans case runs the same inner kernel (Sec. 2.2 "transposed while packed";
-// Sec. 3.2.1: one shared inner kernel for all variants).  On gfx950 the buffer
-// is LDS and the inner kernel is a v_mfma_f64_16x16x4 rank-4 update.
+// trans case runs the same inner kernel (Sec. 2.2: transposition is free while
+// packing; Sec. 3.2.1: one shared inner kernel behind all routines).  On gfx950
+// the buffer is LDS and the inner kernel is a v_mfma_f64_16x16x4 rank-4 update.
 //
-// Packed layout: for a BK x BM slice of op(A) and a BK x BN slice of op(B),
-// element (q, i) lives at As[q*SA + i] and (q, j) at Bs[q*SB + j] (k-major,
-// the "nt" arrangement of both factors).  The MFMA is issued with op(B) as its
-// left operand and op(A) as its right one, so it accumulates C^T tiles whose
-// result registers hold, in lane l, C[16*ti + l%16][16*tj + 4*(l/16) + r]:
-// consecutive lanes own consecutive rows, and the epilogue reads and writes C
-// in 128-byte column segments.
+// Packed layout: a BK (16 or 32) deep slice of op(A) (BM x BK) and of op(B)^T
+// (BN x BK) is stored row by row with k contiguous, As[i][q] and Bs[j][q], row
+// stride SK = BK + 2 doubles (conflict-free 16-byte accesses of 16 consecutive
+// rows).
+// Both factors are therefore in the "nt" arrangement the paper's kernels use.
 //
-// Global->LDS staging maps consecutive threads to consecutive addresses of
-// the operand as stored (rows for 'N' A / 'T' B, k for 'T' A / 'N' B), and the
-// next k-panel is prefetched into registers while the current one is consumed.
-// Two launch shapes share the code:
-//   * SMALL (IPB > 1): each wave owns one whole instance (C up to 16*TM x 16*TN),
+// Inner kernel: the k index seen by MFMA step s in lane group g = lane/16 is
+// q = 4g + s, so every lane fetches its four steps' operands as four
+// consecutive doubles of one packed row (two 128-bit LDS reads per 16x16
+// tile).  The MFMA is issued with op(B) as its left operand and op(A) as its
+// right one, so it accumulates C^T: result register r of lane l holds
+// C[16*ti + l%16][16*tj + l/16 + 4r] -- consecutive lanes own consecutive rows
+// and the epilogue reads/writes C in 128-byte column segments.
+//
+// Pipeline: the next k-panel is loaded from global memory into registers while
+// the current one is multiplied; with two LDS buffers (DB = 2) one workgroup
+// barrier per k-panel suffices.  Each thread stages pairs of consecutive k of
+// one row and writes them with one 16-byte LDS store; operands contiguous
+// along k are also read with 16-byte global loads when every address is
+// 16-byte aligned (VEC = 2).  C is loaded before the k loop (beta != 0) so its
+// latency hides behind the products.
+//
+// Launch shapes:
+//   * WAVE (IPB > 1): each wave owns one whole instance (C up to 16*TM x 16*TN),
 //     IPB instances per workgroup, wave-local synchronisation only;
-//   * TILED (IPB == 1): WM x WN waves cooperate on a BM x BN tile of one
-//     instance, workgroup barriers, XCD-aware tile order.
+//   * TILE (IPB == 1): WM x WN waves cooperate on a BM x BN tile of one
+//     instance; tiles of one instance are numbered consecutively and mapped to
+//     one XCD (shared L2).
 #include "mb_internal.h"
 
 namespace mb {
 
-template <bool TA, bool TB, int WM, int WN, int TM, int TN, int IPB>
+template <int WM_, int WN_, int TM_, int TN_, int IPB_, int BK_, int DB_>
 struct PackedCfg {
+    static constexpr int WM = WM_, WN = WN_, TM = TM_, TN = TN_, IPB = IPB_;
     static constexpr int BM = WM * TM * 16;
     static constexpr int BN = WN * TN * 16;
-    static constexpr int BK = 16;
-    static constexpr int SA = BM + 1;  // odd row stride: transposed stores hit distinct banks
-    static constexpr int SB = BN + 1;
+    static constexpr int BK = BK_;             // k depth of one packed panel (16 or 32)
+    static constexpr int DB = DB_;             // LDS buffers (2: one barrier per panel)
+    static constexpr int SK = BK + 2;          // packed row stride (doubles)
     static constexpr int NTHR = WM * WN * 64;  // threads per instance group
-    static constexpr int EA = BM * BK / NTHR;  // staged elements per thread
-    static constexpr int EB = BN * BK / NTHR;
-    static_assert(EA * NTHR == BM * BK && EB * NTHR == BN * BK, "tile/threads mismatch");
-    static_assert(IPB == 1 || (WM == 1 && WN == 1), "SMALL shape is one wave per instance");
+    static constexpr int LDS_A = BM * SK;
+    static constexpr int LDS_B = BN * SK;
+    static_assert(IPB == 1 || (WM == 1 && WN == 1), "WAVE shape is one wave per instance");
+    static_assert(BK == 16 || BK == 32, "panel depth");
+    static_assert(DB == 1 || DB == 2, "buffers");
 };
 
-template <class Cfg, bool TA>
-__device__ __forceinline__ void load_a(double (&ra)[Cfg::EA], const double *A, size_t lda, int m,
-                                       int k, int i0, int kb, int tid)
-{
-#pragma unroll
-    for (int u = 0; u < Cfg::EA; ++u) {
-        const int e = tid + u * Cfg::NTHR;
-        int i, q;
-        if (!TA) {  // A[i + q*lda]: consecutive threads along i
-            i = e % Cfg::BM;
-            q = e / Cfg::BM;
-        } else {  // A[q + i*lda]: consecutive threads along q
-            q = e % Cfg::BK;
-            i = e / Cfg::BK;
-        }
-        const int gi = i0 + i, gq = kb + q;
-        double v = 0.0;
-        if (gi < m && gq < k)
-            v = TA ? A[(size_t)gq + (size_t)gi * lda] : A[(size_t)gi + (size_t)gq * lda];
-        ra[u] = v;
-    }
-}
+// Stage a ROWS x BK slice of op(X) (rows r0.., k from kb) through registers.
+// op(X)(row, q) = X[row + q*ld] when the rows are contiguous in memory (!T),
+// X[q + row*ld] when k is contiguous (T).  Every thread moves the pair
+// (row, q), (row, q+1) and writes it to LDS with one 16-byte store.
+//   !T: consecutive threads take consecutive rows, so each of the two 8-byte
+//       loads is coalesced across the wave;
+//   T:  consecutive threads take consecutive k pairs; one 16-byte load when
+//       VEC16 (every address 16-byte aligned), else two 8-byte loads.
+template <int ROWS, int NTHR, bool T, bool VEC16, int BK>
+struct Stage {
+    static constexpr int PAIRS = ROWS * BK / 2;
+    static constexpr int PER = PAIRS / NTHR;
+    static_assert(PAIRS % NTHR == 0, "staging must divide evenly");
+    double v[PER][2];
 
-template <class Cfg, bool TA>
-__device__ __forceinline__ void store_a(const double (&ra)[Cfg::EA], double *As, int tid)
-{
-#pragma unroll
-    for (int u = 0; u < Cfg::EA; ++u) {
-        const int e = tid + u * Cfg::NTHR;
-        int i, q;
-        if (!TA) {
-            i = e % Cfg::BM;
-            q = e / Cfg::BM;
+    __device__ __forceinline__ static void coords(int e, int &row, int &q)
+    {
+        if (!T) {
+            row = e % ROWS;
+            q = 2 * (e / ROWS);
         } else {
-            q = e % Cfg::BK;
-            i = e / Cfg::BK;
+            q = 2 * (e % (BK / 2));
+            row = e / (BK / 2);
         }
-        As[q * Cfg::SA + i] = ra[u];
     }
-}
 
-template <class Cfg, bool TB>
-__device__ __forceinline__ void load_b(double (&rb)[Cfg::EB], const double *B, size_t ldb, int n,
-                                       int k, int j0, int kb, int tid)
-{
+    __device__ __forceinline__ void load(const double *X, size_t ld, int nrows, int k, int r0,
+                                         int kb, int tid)
+    {
 #pragma unroll
-    for (int u = 0; u < Cfg::EB; ++u) {
-        const int e = tid + u * Cfg::NTHR;
-        int j, q;
-        if (TB) {  // B[j + q*ldb]: consecutive threads along j
-            j = e % Cfg::BN;
-            q = e / Cfg::BN;
-        } else {  // B[q + j*ldb]: consecutive threads along q
-            q = e % Cfg::BK;
-            j = e / Cfg::BK;
+        for (int u = 0; u < PER; ++u) {
+            int row, q;
+            coords(tid + u * NTHR, row, q);
+            const int gr = r0 + row, gq = kb + q;
+            const bool rin = gr < nrows;
+            const bool in0 = rin && gq < k, in1 = rin && gq + 1 < k;
+            if (!T) {
+                const double *ptr = X + (size_t)gr + (size_t)gq * ld;
+                v[u][0] = in0 ? ptr[0] : 0.0;
+                v[u][1] = in1 ? ptr[ld] : 0.0;
+            } else {
+                const double *ptr = X + (size_t)gq + (size_t)gr * ld;
+                if (VEC16 && in1) {
+                    const double2 w = *reinterpret_cast<const double2 *>(ptr);
+                    v[u][0] = w.x;
+                    v[u][1] = w.y;
+                } else {
+                    v[u][0] = in0 ? ptr[0] : 0.0;
+                    v[u][1] = in1 ? ptr[1] : 0.0;
+                }
+            }
         }
-        const int gj = j0 + j, gq = kb + q;
-        double v = 0.0;
-        if (gj < n && gq < k)
-            v = TB ? B[(size_t)gj + (size_t)gq * ldb] : B[(size_t)gq + (size_t)gj * ldb];
-        rb[u] = v;
     }
-}
 
-template <class Cfg, bool TB>
-__device__ __forceinline__ void store_b(const double (&rb)[Cfg::EB], double *Bs, int tid)
-{
+    template <int SK>
+    __device__ __forceinline__ void store(double *S, int tid) const
+    {
 #pragma unroll
-    for (int u = 0; u < Cfg::EB; ++u) {
-        const int e = tid + u * Cfg::NTHR;
-        int j, q;
-        if (TB) {
-            j = e % Cfg::BN;
-            q = e / Cfg::BN;
-        } else {
-            q = e % Cfg::BK;
-            j = e / Cfg::BK;
+        for (int u = 0; u < PER; ++u) {
+            int row, q;
+            coords(tid + u * NTHR, row, q);
+            *reinterpret_cast<double2 *>(&S[row * SK + q]) = double2{v[u][0], v[u][1]};
         }
-        Bs[q * Cfg::SB + j] = rb[u];
     }
-}
+};
 
-template <bool TA, bool TB, int WM, int WN, int TM, int TN, int IPB>
-__global__ __launch_bounds__(WM *WN *IPB * 64) void gemm_packed_kernel(GemmArgs p, int tiles_m,
-                                                                       int tiles_n)
+template <bool TA, bool TB, class Cfg, int VEC>
+__global__ __launch_bounds__(Cfg::NTHR *Cfg::IPB) void gemm_packed_kernel(GemmArgs p, int tiles_m,
+                                                                          int tiles_n)
 {
-    using Cfg = PackedCfg<TA, TB, WM, WN, TM, TN, IPB>;
+    constexpr int WM = Cfg::WM, WN = Cfg::WN, TM = Cfg::TM, TN = Cfg::TN, IPB = Cfg::IPB;
+    constexpr int BK = Cfg::BK, DB = Cfg::DB;
     constexpr bool WAVE_ONLY = (IPB > 1);
-    __shared__ double smem[IPB][Cfg::BK * Cfg::SA + Cfg::BK * Cfg::SB];
+    constexpr int SK = Cfg::SK;
+    __shared__ __align__(16) double smem[IPB][DB][Cfg::LDS_A + Cfg::LDS_B];
 
     const int lane = threadIdx.x & 63;
     int grp, tid;  // instance group within the block, thread id within it
@@ -152,8 +152,6 @@ __global__ __launch_bounds__(WM *WN *IPB * 64) void gemm_packed_kernel(GemmArgs 
         tn = rem / tiles_m;
         tm = rem - tn * tiles_m;
     }
-    double *As = &smem[grp][0];
-    double *Bs = &smem[grp][Cfg::BK * Cfg::SA];
 
     const double *A = inst_ptr(p.A, p.Aarr, p.sA, b);
     const double *B = inst_ptr(p.B, p.Barr, p.sB, b);
@@ -173,39 +171,84 @@ __global__ __launch_bounds__(WM *WN *IPB * 64) void gemm_packed_kernel(GemmArgs 
         for (int tj = 0; tj < TN; ++tj)
             acc[ti][tj] = d4{0.0, 0.0, 0.0, 0.0};
 
-    double ra[Cfg::EA], rb[Cfg::EB];
-    load_a<Cfg, TA>(ra, A, lda, m, k, i0, 0, tid);
-    load_b<Cfg, TB>(rb, B, ldb, n, k, j0, 0, tid);
-
-    for (int kb = 0; kb < k; kb += Cfg::BK) {
-        store_a<Cfg, TA>(ra, As, tid);
-        store_b<Cfg, TB>(rb, Bs, tid);
-        group_sync<WAVE_ONLY>();
-        if (kb + Cfg::BK < k) {
-            load_a<Cfg, TA>(ra, A, lda, m, k, i0, kb + Cfg::BK, tid);
-            load_b<Cfg, TB>(rb, B, ldb, n, k, j0, kb + Cfg::BK, tid);
-        }
+    // C is only needed by the epilogue: issue its loads first so that their
+    // latency hides behind the whole k loop.
+    const double alpha = p.alpha, beta = p.beta;
+    d4 cin[TM][TN];
+    if (beta != 0.0) {
 #pragma unroll
-        for (int s = 0; s < Cfg::BK / 4; ++s) {
-            const int q = 4 * s + lg;
-            double fa[TM], fb[TN];
-#pragma unroll
-            for (int ti = 0; ti < TM; ++ti)
-                fa[ti] = As[q * Cfg::SA + (wm * TM + ti) * 16 + lr];
+        for (int ti = 0; ti < TM; ++ti) {
+            const int gi = i0 + (wm * TM + ti) * 16 + lr;
 #pragma unroll
             for (int tj = 0; tj < TN; ++tj)
-                fb[tj] = Bs[q * Cfg::SB + (wn * TN + tj) * 16 + lr];
 #pragma unroll
-            for (int ti = 0; ti < TM; ++ti)
-#pragma unroll
-                for (int tj = 0; tj < TN; ++tj)
-                    acc[ti][tj] = mfma16(fb[tj], fa[ti], acc[ti][tj]);
+                for (int r = 0; r < 4; ++r) {
+                    const int gj = j0 + (wn * TN + tj) * 16 + lg + 4 * r;
+                    cin[ti][tj][r] = (gi < m && gj < n) ? C[(size_t)gi + (size_t)gj * ldc] : 0.0;
+                }
         }
-        group_sync<WAVE_ONLY>();
+    }
+
+    Stage<Cfg::BM, Cfg::NTHR, TA, VEC == 2, BK> sa;   // op(A): rows i; 'T' A is contiguous along k
+    Stage<Cfg::BN, Cfg::NTHR, !TB, VEC == 2, BK> sb;  // op(B)^T: rows j; 'N' B: contiguous along k
+    sa.load(A, lda, m, k, i0, 0, tid);
+    sb.load(B, ldb, n, k, j0, 0, tid);
+    sa.template store<SK>(&smem[grp][0][0], tid);
+    sb.template store<SK>(&smem[grp][0][Cfg::LDS_A], tid);
+    group_sync<WAVE_ONLY>();
+
+    int cur = 0;
+    for (int kb = 0; kb < k; kb += BK) {
+        const bool more = kb + BK < k;
+        if (more) {
+            sa.load(A, lda, m, k, i0, kb + BK, tid);
+            sb.load(B, ldb, n, k, j0, kb + BK, tid);
+        }
+        const double *As = &smem[grp][cur][0];
+        const double *Bs = &smem[grp][cur][Cfg::LDS_A];
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 16) {
+            double fa[TM][4], fb[TN][4];
+#pragma unroll
+            for (int ti = 0; ti < TM; ++ti) {
+                const double *src = &As[((wm * TM + ti) * 16 + lr) * SK + kk + 4 * lg];
+                const double2 x = *reinterpret_cast<const double2 *>(src);
+                const double2 y = *reinterpret_cast<const double2 *>(src + 2);
+                fa[ti][0] = x.x;
+                fa[ti][1] = x.y;
+                fa[ti][2] = y.x;
+                fa[ti][3] = y.y;
+            }
+#pragma unroll
+            for (int tj = 0; tj < TN; ++tj) {
+                const double *src = &Bs[((wn * TN + tj) * 16 + lr) * SK + kk + 4 * lg];
+                const double2 x = *reinterpret_cast<const double2 *>(src);
+                const double2 y = *reinterpret_cast<const double2 *>(src + 2);
+                fb[tj][0] = x.x;
+                fb[tj][1] = x.y;
+                fb[tj][2] = y.x;
+                fb[tj][3] = y.y;
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < TN; ++tj)
+                        acc[ti][tj] = mfma16(fb[tj][s], fa[ti][s], acc[ti][tj]);
+        }
+        if (more) {
+            if constexpr (DB == 1)
+                group_sync<WAVE_ONLY>();  // everyone is done reading the single buffer
+            const int nxt = (DB == 2) ? (cur ^ 1) : 0;
+            sa.template store<SK>(&smem[grp][nxt][0], tid);
+            sb.template store<SK>(&smem[grp][nxt][Cfg::LDS_A], tid);
+            group_sync<WAVE_ONLY>();
+            cur = nxt;
+        }
     }
 
     // epilogue: C <= alpha*acc + beta*C, masked to the m x n window
-    const double alpha = p.alpha, beta = p.beta;
 #pragma unroll
     for (int ti = 0; ti < TM; ++ti) {
         const int gi = i0 + (wm * TM + ti) * 16 + lr;
@@ -215,76 +258,130 @@ __global__ __launch_bounds__(WM *WN *IPB * 64) void gemm_packed_kernel(GemmArgs 
             for (int r = 0; r < 4; ++r) {
                 const int gj = j0 + (wn * TN + tj) * 16 + lg + 4 * r;
                 if (gi < m && gj < n) {
-                    double *c = C + (size_t)gi + (size_t)gj * ldc;
                     const double v = acc[ti][tj][r];
-                    *c = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * (*c));
+                    C[(size_t)gi + (size_t)gj * ldc] =
+                        (beta == 0.0) ? alpha * v : fma(alpha, v, beta * cin[ti][tj][r]);
                 }
             }
         }
     }
 }
 
-template <bool TA, bool TB, int WM, int WN, int TM, int TN, int IPB>
+// ---------------------------------------------------------------- launch ---
+
+// The menu of packed configurations.  Each entry: waves (WM x WN), MFMA tiles
+// per wave (TM x TN), instances per workgroup (IPB > 1: one wave per instance),
+// panel depth BK and LDS buffers DB.  The default choice per size class is the
+// measured table in gemm_tuned.h (written by the autotuner).
+#define MB_PACKED_CONFIGS(X)                                                                \
+    X(0, "wave16", 1, 1, 1, 1, 4, 16, 1)                                                     \
+    X(1, "wave32", 1, 1, 2, 2, 4, 16, 1)                                                     \
+    X(2, "wave48", 1, 1, 3, 3, 2, 16, 1)                                                     \
+    X(3, "tile64_k16", 2, 2, 2, 2, 1, 16, 1)                                                 \
+    X(4, "tile64_k32", 2, 2, 2, 2, 1, 32, 1)                                                 \
+    X(5, "tile64_k16_db", 2, 2, 2, 2, 1, 16, 2)                                              \
+    X(6, "tile96_k16", 2, 2, 3, 3, 1, 16, 1)                                                 \
+    X(7, "tile128_w4", 2, 2, 4, 4, 1, 16, 1)                                                 \
+    X(8, "tile128_w8", 2, 4, 4, 2, 1, 16, 1)                                                 \
+    X(9, "tile128_w8_db", 2, 4, 4, 2, 1, 16, 2)                                              \
+    X(10, "tile64x128_w8", 2, 4, 2, 2, 1, 16, 1)                                             \
+    X(11, "tile96_k32", 2, 2, 3, 3, 1, 32, 1)
+
+#define MB_COUNT_CFG(id, name, wm, wn, tm, tn, ipb, bk, db) +1
+constexpr int kPackedConfigs = 0 MB_PACKED_CONFIGS(MB_COUNT_CFG);
+
+// 16-byte global loads need every instance base, stride and leading dimension
+// of A and B to keep 16-byte alignment (pointer arrays are not inspected on
+// the host: they use 8-byte loads).
+static bool vec2_ok(const GemmArgs &a)
+{
+    if (a.Aarr || a.Barr)
+        return false;
+    const uintptr_t pa = (uintptr_t)a.A, pb = (uintptr_t)a.B;
+    return (pa % 16 == 0) && (pb % 16 == 0) && (a.lda % 2 == 0) && (a.ldb % 2 == 0) &&
+           (a.sA % 2 == 0) && (a.sB % 2 == 0);
+}
+
+template <bool TA, bool TB, class Cfg>
 static hipError_t launch_cfg(const GemmArgs &a, hipStream_t s)
 {
-    using Cfg = PackedCfg<TA, TB, WM, WN, TM, TN, IPB>;
-    if constexpr (IPB > 1) {
-        const int64_t blocks = ((int64_t)a.batch + IPB - 1) / IPB;
-        hipLaunchKernelGGL((gemm_packed_kernel<TA, TB, WM, WN, TM, TN, IPB>), dim3((unsigned)blocks),
-                           dim3(64 * IPB), 0, s, a, 1, 1);
+    const bool v2 = vec2_ok(a);
+    int tiles_m = 1, tiles_n = 1;
+    int64_t blocks;
+    if constexpr (Cfg::IPB > 1) {
+        blocks = ((int64_t)a.batch + Cfg::IPB - 1) / Cfg::IPB;
+        if (a.m > Cfg::BM || a.n > Cfg::BN)
+            return hipErrorInvalidValue;  // a wave owns a whole instance
     } else {
-        const int tiles_m = (a.m + Cfg::BM - 1) / Cfg::BM;
-        const int tiles_n = (a.n + Cfg::BN - 1) / Cfg::BN;
-        const int64_t blocks = (int64_t)a.batch * tiles_m * tiles_n;
-        if (blocks > 0x7fffffff)
-            return hipErrorInvalidValue;
-        hipLaunchKernelGGL((gemm_packed_kernel<TA, TB, WM, WN, TM, TN, 1>), dim3((unsigned)blocks),
-                           dim3(64 * WM * WN), 0, s, a, tiles_m, tiles_n);
+        tiles_m = (a.m + Cfg::BM - 1) / Cfg::BM;
+        tiles_n = (a.n + Cfg::BN - 1) / Cfg::BN;
+        blocks = (int64_t)a.batch * tiles_m * tiles_n;
     }
+    if (blocks > 0x7fffffff)
+        return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks), block(Cfg::NTHR * Cfg::IPB);
+    if (v2)
+        hipLaunchKernelGGL((gemm_packed_kernel<TA, TB, Cfg, 2>), grid, block, 0, s, a, tiles_m,
+                           tiles_n);
+    else
+        hipLaunchKernelGGL((gemm_packed_kernel<TA, TB, Cfg, 1>), grid, block, 0, s, a, tiles_m,
+                           tiles_n);
     return hipGetLastError();
 }
 
-// Tile configuration by operand size (the packed family's own size classes).
-enum PackedConfig { PK_WAVE16 = 0, PK_WAVE32 = 1, PK_TILE64 = 2 };
-
-static PackedConfig packed_config(int m, int n)
-{
-    const int mx = m > n ? m : n;
-    if (mx <= 16)
-        return PK_WAVE16;
-    if (mx <= 32)
-        return PK_WAVE32;
-    return PK_TILE64;
-}
-
 template <bool TA, bool TB>
-static hipError_t launch_packed_t(const GemmArgs &a, hipStream_t s)
+static hipError_t launch_config_t(int config, const GemmArgs &a, hipStream_t s)
 {
-    switch (packed_config(a.m, a.n)) {
-    case PK_WAVE16: return launch_cfg<TA, TB, 1, 1, 1, 1, 4>(a, s);
-    case PK_WAVE32: return launch_cfg<TA, TB, 1, 1, 2, 2, 4>(a, s);
-    default: return launch_cfg<TA, TB, 2, 2, 2, 2, 1>(a, s);
+    switch (config) {
+#define MB_CASE_CFG(id, name, wm, wn, tm, tn, ipb, bk, db)                                     \
+    case id:                                                                                \
+        return launch_cfg<TA, TB, PackedCfg<wm, wn, tm, tn, ipb, bk, db>>(a, s);
+        MB_PACKED_CONFIGS(MB_CASE_CFG)
+#undef MB_CASE_CFG
+    default:
+        return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_gemm_packed(bool ta, bool tb, const GemmArgs &a, hipStream_t s)
+int packed_config_count() { return kPackedConfigs; }
+
+const char *packed_config_name(int config)
+{
+    switch (config) {
+#define MB_NAME_CFG(id, name, wm, wn, tm, tn, ipb, bk, db) \
+    case id:                                              \
+        return "gemm_packed_" name;
+        MB_PACKED_CONFIGS(MB_NAME_CFG)
+#undef MB_NAME_CFG
+    default:
+        return "illegal";
+    }
+}
+
+// Largest C a configuration can take in one wave (WAVE shapes) or 0 (TILE).
+int packed_config_wave_limit(int config)
+{
+    switch (config) {
+#define MB_LIM_CFG(id, name, wm, wn, tm, tn, ipb, bk, db) \
+    case id:                                             \
+        return ipb > 1 ? tm * 16 : 0;
+        MB_PACKED_CONFIGS(MB_LIM_CFG)
+#undef MB_LIM_CFG
+    default:
+        return -1;
+    }
+}
+
+hipError_t launch_gemm_packed_config(int config, bool ta, bool tb, const GemmArgs &a,
+                                     hipStream_t s)
 {
     if (!ta && !tb)
-        return launch_packed_t<false, false>(a, s);
+        return launch_config_t<false, false>(config, a, s);
     if (!ta && tb)
-        return launch_packed_t<false, true>(a, s);
+        return launch_config_t<false, true>(config, a, s);
     if (ta && !tb)
-        return launch_packed_t<true, false>(a, s);
-    return launch_packed_t<true, true>(a, s);
-}
-
-const char *packed_kernel_name(int m, int n)
-{
-    switch (packed_config(m, n)) {
-    case PK_WAVE16: return "gemm_packed_wave16";
-    case PK_WAVE32: return "gemm_packed_wave32";
-    default: return "gemm_packed_tile64";
-    }
+        return launch_config_t<true, false>(config, a, s);
+    return launch_config_t<true, true>(config, a, s);
 }
 
 }  // namespace mb

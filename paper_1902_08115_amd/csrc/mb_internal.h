@@ -90,13 +90,18 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk)
 
 // ---- launchers (host) -------------------------------------------------------
 hipError_t launch_gemm_direct(bool ta, bool tb, const GemmArgs &a, hipStream_t s);
-hipError_t launch_gemm_packed(bool ta, bool tb, const GemmArgs &a, hipStream_t s);
+hipError_t launch_gemm_packed_config(int config, bool ta, bool tb, const GemmArgs &a,
+                                     hipStream_t s);
 hipError_t launch_gemm_scale(const GemmArgs &a, hipStream_t s);
 hipError_t launch_potrf_lower(const PotrfArgs &a, hipStream_t s);
 hipError_t launch_fill_info(int *info, int batch, hipStream_t s);
 
-// Names of the kernel classes a call is dispatched to (profiling attribution).
-const char *packed_kernel_name(int m, int n);
+// The packed configuration menu (gemm_packed.hip).
+int packed_config_count();
+const char *packed_config_name(int config);
+int packed_config_wave_limit(int config);  // > 0: largest m, n of a WAVE shape; 0: any
+
+// Name of the potrf kernel class for order n (profiling attribution).
 const char *potrf_kernel_name(int n);
 
 // Largest order handled by the register-resident Cholesky kernel.

@@ -7,35 +7,40 @@
 // block and a lower-triangle store (Sec. 3.2.1); off-diagonal blocks use the
 // right-variant triangular solve, which vectorizes across rows (Sec. 3.1.3).
 //
-// gfx950 design: one kernel launch factors every instance of the batch; one
-// group of NW waves factors one instance, blocked in 16 x 16 tiles (the FP64
-// MFMA tile), right-looking, with the whole lower triangle resident in the
-// matrix-core accumulator registers of the group's waves (tile (I,K) is owned
-// by wave t % NW, t its column-major index among lower tiles).  Step J:
-//   1. the owner of tile (J,J) factors it in registers, lanes over rows and
-//      readlane broadcasts (inner_edge_dpotrf), and also forms L_JJ^{-1};
-//   2. panel tiles (I,J), I > J: X = A_IJ * L_JJ^{-T}, four MFMA steps whose
-//      right operand is the tile's own accumulator registers (right-variant
-//      solve expressed as a product with the inverted diagonal block);
-//   3. trailing tiles (I,K), J < K <= I: acc -= X_I * X_K^T, four MFMA steps
-//      reading both panel tiles from LDS (the dgemm_nt inner update).
-// The matrix is read once and written once; the strict upper triangle is never
-// accessed.  Orders that are not a multiple of 16 are padded with the identity,
-// which the factorization leaves unchanged.  The first non-positive (or NaN)
-// pivot stops the instance and is reported as info = column + 1 (LAPACK).
+// gfx950 design: one launch factors the whole batch, one wave per instance,
+// several instances per workgroup, blocked in 16 x 16 tiles (the FP64 MFMA
+// tile) and left-looking, so only a few tiles live in the wave's registers and
+// many instances share a CU (their serial pivot chains hide behind each
+// other's matrix-core work).  Tiles are held in accumulator order -- lane
+// (g, i), register r holds element (16I + i, 16J + g + 4r).  Step J:
+//   1. tile(J,J) of A minus L(J,K) * L(J,K)^T for every factored block column
+//      K < J: four MFMA steps per K whose operands are the registers s of
+//      L(J,K) loaded from the factor already written (the k index of step s in
+//      lane group g is g + 4s: the accumulator order itself, so no reshuffle);
+//   2. factor the diagonal tile in registers and form L_JJ^{-1} alongside
+//      (inner_edge_dpotrf); write the lower part of L_JJ;
+//   3. panel tiles I > J, four at a time: tile(I,J) of A minus
+//      L(I,K) * L(J,K)^T for K < J (the dgemm_nt inner update, alpha = -1,
+//      beta = 1), then L(I,J) = tile(I,J) * L_JJ^{-T}, four MFMA steps with
+//      L_JJ^{-1} (also in accumulator order) as the left operand -- the
+//      right-variant solve expressed as a product with the inverted diagonal
+//      block; write L(I,J).
+// Only the lower triangle is read or written.  Orders that are not a multiple
+// of 16 are padded with the identity, which the factorization leaves
+// unchanged.  The first non-positive (or NaN) pivot stops the instance and is
+// reported as info = column + 1 (LAPACK).
 #include <limits.h>
 
 #include "mb_internal.h"
 
 namespace mb {
 
-template <int NT, int PB>
+// Per-wave LDS for broadcasting the column being eliminated in the diagonal
+// tile (double-buffered by column parity).
 struct PotrfSmem {
-    double col[2][16];        // column being eliminated (diagonal tile)
-    double xrow[2][16];       // row of L^{-1} being propagated (diagonal tile)
-    double W[4][64];          // L_JJ^{-1} in MFMA left-operand order, per k-step
-    double P[PB][NT][4][64];  // panel tiles X_I in accumulator order [reg][lane]
-    int fail;                 // first failing global column, INT_MAX if none
+    double col[2][16];   // column being eliminated (diagonal tile)
+    double xrow[2][16];  // row of L^{-1} being propagated (diagonal tile)
+    int fail;            // first failing global column, INT_MAX if none
 };
 
 // Factor one 16x16 diagonal tile held in accumulator order -- lane (g, i),
@@ -119,143 +124,116 @@ __device__ __forceinline__ void factor_diag_tile(d4 &t, d4 &x, Smem &S, int J, i
             t[r] = 0.0;
 }
 
-template <int NT, int NW, int IPB>
-__global__ __launch_bounds__(NW *IPB * 64) void potrf_lower_kernel(PotrfArgs p)
+// Load tile (I, K) in accumulator order.  diag: the tile of A on the
+// diagonal (strict upper part read as zero); outside the n x n matrix the
+// identity is used.
+__device__ __forceinline__ d4 load_tile(const double *A, size_t lda, int n, int I, int K,
+                                        int lr, int lg, bool diag)
 {
-    constexpr int T = NT * (NT + 1) / 2;
-    constexpr int SLOTS = (T + NW - 1) / NW;
-    constexpr bool WAVE_ONLY = (NW == 1);
-    constexpr int PB = WAVE_ONLY ? 1 : 2;
-    static_assert(IPB == 1 || NW == 1, "several instances per block only with one wave each");
-    __shared__ PotrfSmem<NT, PB> smem[IPB];
+    d4 t;
+    const int gi = 16 * I + lr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int gc = 16 * K + lg + 4 * r;
+        double v = 0.0;
+        if (gi < n && gc < n) {
+            if (!diag || gi >= gc)
+                v = A[(size_t)gi + (size_t)gc * lda];
+        } else if (gi == gc) {
+            v = 1.0;
+        }
+        t[r] = v;
+    }
+    return t;
+}
 
+template <int NT, int IPB>
+__global__ __launch_bounds__(IPB * 64) void potrf_lower_kernel(PotrfArgs p)
+{
+    constexpr int G = 4;  // panel tiles updated together (shared L(J,K) operand)
+    __shared__ PotrfSmem smem[IPB];
     const int lane = threadIdx.x & 63;
-    const int wib = threadIdx.x >> 6;
-    const int inst = wib / NW;
-    const int w = __builtin_amdgcn_readfirstlane(wib - inst * NW);
+    const int inst = threadIdx.x >> 6;
     const int64_t b = (int64_t)blockIdx.x * IPB + inst;
     if (b >= p.batch)
-        return;  // IPB > 1 implies NW == 1: this whole wave is idle
-    PotrfSmem<NT, PB> &S = smem[inst];
+        return;  // each wave is its own instance: nothing to synchronise with
+    PotrfSmem &S = smem[inst];
     double *A = inst_ptr(p.A, p.Aarr, p.sA, b);
     const int n = p.n;
     const size_t lda = (size_t)p.lda;
     const int lr = lane & 15, lg = lane >> 4;
-
-    // slot -> tile (I, K); -1 when the slot is unused
-    int tI[SLOTS], tK[SLOTS];
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-        int t = w + s * NW;
-        tI[s] = -1;
-        tK[s] = -1;
-        if (t < T) {
-            int K = 0;
-            while (t >= NT - K) {
-                t -= NT - K;
-                ++K;
-            }
-            tK[s] = K;
-            tI[s] = K + t;
-        }
-    }
-
-    // load the owned tiles in accumulator order: lane (lg, lr), reg r holds
-    // element (16I + lr, 16K + lg + 4r); identity outside the n x n matrix and
-    // zeros in the strict upper part of diagonal tiles.
-    d4 acc[SLOTS];
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            double v = 0.0;
-            if (tI[s] >= 0) {
-                const int gi = 16 * tI[s] + lr, gc = 16 * tK[s] + lg + 4 * r;
-                if (gi < n && gc < n) {
-                    if (gi >= gc)
-                        v = A[(size_t)gi + (size_t)gc * lda];
-                } else if (gi == gc) {
-                    v = 1.0;
-                }
-            }
-            acc[s][r] = v;
-        }
-    }
-    if (w == 0 && lane == 0)
+    if (lane == 0)
         S.fail = INT_MAX;
-    group_sync<WAVE_ONLY>();
+    wave_lds_sync();
 
     for (int J = 0; J < NT; ++J) {
-        const int pb = WAVE_ONLY ? 0 : (J & 1);
-        // 1. diagonal tile: its owner factors it and forms L_JJ^{-1}
-        {
-            bool own = false;
-            d4 t = d4{0.0, 0.0, 0.0, 0.0};
+        // 1-3. diagonal tile: update with the factored columns, then factor it
+        d4 t = load_tile(A, lda, n, J, J, lr, lg, true);
+#pragma unroll 2
+        for (int K = 0; K < J; ++K) {
+            const d4 lj = load_tile(A, lda, n, J, K, lr, lg, false);
 #pragma unroll
-            for (int s = 0; s < SLOTS; ++s) {
-                if (tI[s] == J && tK[s] == J) {
-                    own = true;
-                    t = acc[s];
-                }
-            }
-            if (own) {
-                d4 x;
-                factor_diag_tile(t, x, S, J, lane);
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    S.W[r][lane] = x[r];
-                // store the lower part of L_JJ (columns before a failing pivot only)
-                wave_lds_sync();
-                const int fail_col = S.fail;
-                const int gi = 16 * J + lr;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int gc = 16 * J + lg + 4 * r;
-                    if (gi < n && gc <= gi && gc < fail_col)
-                        A[(size_t)gi + (size_t)gc * lda] = t[r];
-                }
-            }
+            for (int s = 0; s < 4; ++s)
+                t = mfma16(-lj[s], lj[s], t);
         }
-        group_sync<WAVE_ONLY>();
-        // 2. panel tiles: X = A_IJ * L_JJ^{-T}; after a failing pivot only the
-        //    columns before it are meaningful and stored
+        d4 x;
+        factor_diag_tile(t, x, S, J, lane);
+        wave_lds_sync();
         const int fail_col = S.fail;
+        {
+            const int gi = 16 * J + lr;
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-            if (tK[s] == J && tI[s] > J) {
-                d4 x = d4{0.0, 0.0, 0.0, 0.0};
+            for (int r = 0; r < 4; ++r) {
+                const int gc = 16 * J + lg + 4 * r;
+                if (gi < n && gc <= gi && gc < fail_col)
+                    A[(size_t)gi + (size_t)gc * lda] = t[r];
+            }
+        }
+        // 2 + 4. panel tiles, G at a time: update, then L(I,J) = tile * L_JJ^{-T}
+        for (int I0 = J + 1; I0 < NT; I0 += G) {
+            d4 acc[G];
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    x = mfma16(S.W[q][lane], acc[s][q], x);
-                acc[s] = x;
-                const int gi = 16 * tI[s] + lr;
+            for (int g = 0; g < G; ++g)
+                acc[g] = (I0 + g < NT) ? load_tile(A, lda, n, I0 + g, J, lr, lg, false)
+                                       : d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+            for (int K = 0; K < J; ++K) {
+                const d4 lj = load_tile(A, lda, n, J, K, lr, lg, false);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    S.P[pb][tI[s]][r][lane] = x[r];
-                    const int gc = 16 * J + lg + 4 * r;
-                    if (gi < n && gc < n && gc < fail_col)
-                        A[(size_t)gi + (size_t)gc * lda] = x[r];
+                for (int g = 0; g < G; ++g) {
+                    if (I0 + g < NT) {
+                        const d4 li = load_tile(A, lda, n, I0 + g, K, lr, lg, false);
+#pragma unroll
+                        for (int s = 0; s < 4; ++s)
+                            acc[g] = mfma16(-lj[s], li[s], acc[g]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                if (I0 + g < NT) {
+                    d4 xo = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        xo = mfma16(x[s], acc[g][s], xo);
+                    const int gi = 16 * (I0 + g) + lr;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int gc = 16 * J + lg + 4 * r;
+                        if (gi < n && gc < n && gc < fail_col)
+                            A[(size_t)gi + (size_t)gc * lda] = xo[r];
+                    }
                 }
             }
         }
-        group_sync<WAVE_ONLY>();
-        // a failure at this step's pivot ends the instance; a later step's
-        // diagonal owner may already be writing S.fail, hence the bound
-        if (S.fail < 16 * (J + 1))
+        if (fail_col != INT_MAX || J == NT - 1)
             break;
-        // 3. trailing update: acc(I,K) -= X_I * X_K^T for J < K <= I
-#pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-            if (tK[s] > J) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    acc[s] = mfma16(-S.P[pb][tK[s]][q][lane], S.P[pb][tI[s]][q][lane], acc[s]);
-            }
-        }
-        if constexpr (WAVE_ONLY)
-            wave_lds_sync();
+        // the next steps read this block column back: make the stores visible
+        // to this wave's later loads (complete them, drop stale L1 lines)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    if (w == 0 && lane == 0)
+    if (lane == 0)
         p.info[b] = (S.fail == INT_MAX) ? 0 : S.fail + 1;
 }
 
@@ -266,12 +244,12 @@ __global__ void fill_info_kernel(int *info, int batch)
         info[i] = 0;
 }
 
-template <int NT, int NW, int IPB>
+template <int NT, int IPB>
 static hipError_t launch_potrf_t(const PotrfArgs &a, hipStream_t s)
 {
     const int64_t blocks = ((int64_t)a.batch + IPB - 1) / IPB;
-    hipLaunchKernelGGL((potrf_lower_kernel<NT, NW, IPB>), dim3((unsigned)blocks),
-                       dim3(64 * NW * IPB), 0, s, a);
+    hipLaunchKernelGGL((potrf_lower_kernel<NT, IPB>), dim3((unsigned)blocks), dim3(64 * IPB), 0, s,
+                       a);
     return hipGetLastError();
 }
 
@@ -279,25 +257,25 @@ hipError_t launch_potrf_lower(const PotrfArgs &a, hipStream_t s)
 {
     const int nt = (a.n + 15) / 16;
     switch (nt) {
-    case 1: return launch_potrf_t<1, 1, 4>(a, s);
-    case 2: return launch_potrf_t<2, 1, 4>(a, s);
-    case 3: return launch_potrf_t<3, 1, 4>(a, s);
-    case 4: return launch_potrf_t<4, 1, 4>(a, s);
-    case 5: return launch_potrf_t<5, 4, 1>(a, s);
-    case 6: return launch_potrf_t<6, 4, 1>(a, s);
-    case 7: return launch_potrf_t<7, 4, 1>(a, s);
-    case 8: return launch_potrf_t<8, 4, 1>(a, s);
-    case 9: return launch_potrf_t<9, 8, 1>(a, s);
-    case 10: return launch_potrf_t<10, 8, 1>(a, s);
-    case 11: return launch_potrf_t<11, 8, 1>(a, s);
-    case 12: return launch_potrf_t<12, 8, 1>(a, s);
-    case 13: return launch_potrf_t<13, 16, 1>(a, s);
-    case 14: return launch_potrf_t<14, 16, 1>(a, s);
-    case 15: return launch_potrf_t<15, 16, 1>(a, s);
-    case 16: return launch_potrf_t<16, 16, 1>(a, s);
-    case 17: return launch_potrf_t<17, 16, 1>(a, s);
-    case 18: return launch_potrf_t<18, 16, 1>(a, s);
-    case 19: return launch_potrf_t<19, 16, 1>(a, s);
+    case 1: return launch_potrf_t<1, 4>(a, s);
+    case 2: return launch_potrf_t<2, 4>(a, s);
+    case 3: return launch_potrf_t<3, 4>(a, s);
+    case 4: return launch_potrf_t<4, 4>(a, s);
+    case 5: return launch_potrf_t<5, 4>(a, s);
+    case 6: return launch_potrf_t<6, 4>(a, s);
+    case 7: return launch_potrf_t<7, 4>(a, s);
+    case 8: return launch_potrf_t<8, 4>(a, s);
+    case 9: return launch_potrf_t<9, 4>(a, s);
+    case 10: return launch_potrf_t<10, 4>(a, s);
+    case 11: return launch_potrf_t<11, 4>(a, s);
+    case 12: return launch_potrf_t<12, 4>(a, s);
+    case 13: return launch_potrf_t<13, 4>(a, s);
+    case 14: return launch_potrf_t<14, 4>(a, s);
+    case 15: return launch_potrf_t<15, 4>(a, s);
+    case 16: return launch_potrf_t<16, 4>(a, s);
+    case 17: return launch_potrf_t<17, 4>(a, s);
+    case 18: return launch_potrf_t<18, 4>(a, s);
+    case 19: return launch_potrf_t<19, 4>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

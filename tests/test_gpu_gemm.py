@@ -232,3 +232,36 @@ def test_full_batch_sampled(trans):
             assert np.linalg.norm(Cg[j] - Cr) / scale <= GEMM_TOL
         del A, B, C
         torch.cuda.empty_cache()
+
+
+def test_every_packed_config_exact():
+    """Every configuration of the packed kernel menu (the autotuner's search
+    space), every trans case, ragged shapes spanning several tiles and panels:
+    bit-exact on integer data; 8-byte-load path via odd leading dimensions."""
+    torch, _lib, _ = torch_mods()
+    s = torch.cuda.current_stream().cuda_stream
+    g = inputs.rng(7500)
+    for cfg in range(_lib.dgemm_config_count()):
+        name = _lib.dgemm_config_name(cfg)
+        lim = {"gemm_packed_wave16": 16, "gemm_packed_wave32": 32, "gemm_packed_wave48": 48}.get(
+            name, 300)
+        shapes = [(min(lim, 13), min(lim, 9), 37), (lim, lim, 16), (min(lim, 150), min(lim, 70), 45)]
+        for trans in TRANS:
+            ta, tb = trans
+            for (m, n, k), pad in zip(shapes, (0, 1, 0)):
+                batch = 2
+                A, B, C = _make(g, ta, tb, m, n, k, batch, pad=pad, gap=1, integer=True)
+                dA, dB, dC = dev(A), dev(B), dev(C)
+                say(f"dgemm config {name} {trans} {m}x{n}x{k} pad={pad}")
+                st = _lib.dgemm_strided_batched_config(
+                    ta, tb, m, n, k, 1.0, dA.data_ptr(), A.shape[2], A.shape[1] * A.shape[2],
+                    dB.data_ptr(), B.shape[2], B.shape[1] * B.shape[2], -0.5, dC.data_ptr(),
+                    C.shape[2], C.shape[1] * C.shape[2], batch, cfg, s)
+                assert st == 0, (name, st)
+                Cg = host(dC).reshape(C.shape)
+                Cr = oracle_gemm_batch(ta, tb, m, n, k, 1.0, A, A.shape[2], B, B.shape[2], -0.5,
+                                       C, C.shape[2], batch)
+                assert np.array_equal(Cg, Cr, equal_nan=True), (name, trans, m, n, k)
+    # a WAVE configuration refuses an instance larger than its tile
+    assert _lib.dgemm_strided_batched_config("N", "N", 17, 17, 4, 1.0, 16, 17, 289, 16, 4, 68,
+                                             0.0, 16, 17, 289, 1, 0, s) == _lib.MB_ERR_UNSUPPORTED
