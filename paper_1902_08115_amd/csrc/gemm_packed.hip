@@ -285,7 +285,10 @@ __global__ __launch_bounds__(Cfg::NTHR *Cfg::IPB) void gemm_packed_kernel(GemmAr
     X(8, "tile128_w8", 2, 4, 4, 2, 1, 16, 1)                                                 \
     X(9, "tile128_w8_db", 2, 4, 4, 2, 1, 16, 2)                                              \
     X(10, "tile64x128_w8", 2, 4, 2, 2, 1, 16, 1)                                             \
-    X(11, "tile96_k32", 2, 2, 3, 3, 1, 32, 1)
+    X(11, "tile96_k32", 2, 2, 3, 3, 1, 32, 1)                                                 \
+    X(12, "tile128_w8_k32", 2, 4, 4, 2, 1, 32, 1)                                            \
+    X(13, "tile64x128_w8_k32", 2, 4, 2, 2, 1, 32, 1)                                         \
+    X(14, "tile128_w4_k32", 2, 2, 4, 4, 1, 32, 1)
 
 #define MB_COUNT_CFG(id, name, wm, wn, tm, tn, ipb, bk, db) +1
 constexpr int kPackedConfigs = 0 MB_PACKED_CONFIGS(MB_COUNT_CFG);

@@ -12,7 +12,9 @@
 // tile) and left-looking, so only a few tiles live in the wave's registers and
 // many instances share a CU (their serial pivot chains hide behind each
 // other's matrix-core work).  Tiles are held in accumulator order -- lane
-// (g, i), register r holds element (16I + i, 16J + g + 4r).  Step J:
+// (g, i), register r holds element (16I + i, 16J + g + 4r).  Block columns
+// are processed two at a time, so every factored tile loaded for the update
+// serves both (half the re-reads of the factor).  For one block column J:
 //   1. tile(J,J) of A minus L(J,K) * L(J,K)^T for every factored block column
 //      K < J: four MFMA steps per K whose operands are the registers s of
 //      L(J,K) loaded from the factor already written (the k index of step s in
@@ -147,10 +149,55 @@ __device__ __forceinline__ d4 load_tile(const double *A, size_t lda, int n, int 
     return t;
 }
 
-template <int NT, int IPB>
-__global__ __launch_bounds__(IPB * 64) void potrf_lower_kernel(PotrfArgs p)
+// Store the lower part of a diagonal tile (columns before a failing pivot).
+__device__ __forceinline__ void store_diag(double *A, size_t lda, int n, int J, const d4 &t,
+                                           int fail_col, int lr, int lg)
 {
-    constexpr int G = 4;  // panel tiles updated together (shared L(J,K) operand)
+    const int gi = 16 * J + lr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int gc = 16 * J + lg + 4 * r;
+        if (gi < n && gc <= gi && gc < fail_col)
+            A[(size_t)gi + (size_t)gc * lda] = t[r];
+    }
+}
+
+// Store an off-diagonal tile (I, J) of L (columns before a failing pivot).
+__device__ __forceinline__ void store_tile(double *A, size_t lda, int n, int I, int J, const d4 &t,
+                                           int fail_col, int lr, int lg)
+{
+    const int gi = 16 * I + lr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int gc = 16 * J + lg + 4 * r;
+        if (gi < n && gc < n && gc < fail_col)
+            A[(size_t)gi + (size_t)gc * lda] = t[r];
+    }
+}
+
+// tile * W^T with W = L_JJ^{-1} in accumulator order (the right-variant solve).
+__device__ __forceinline__ d4 solve_right(const d4 &tile, const d4 &w)
+{
+    d4 xo = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        xo = mfma16(w[s], tile[s], xo);
+    return xo;
+}
+
+// acc -= X * Y^T for two tiles in accumulator order.
+__device__ __forceinline__ d4 update_nt(d4 acc, const d4 &x, const d4 &y)
+{
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        acc = mfma16(-y[s], x[s], acc);
+    return acc;
+}
+
+template <int NT, int IPB>
+__global__ __launch_bounds__(IPB * 64) __attribute__((amdgpu_waves_per_eu(2))) void potrf_lower_kernel(PotrfArgs p)
+{
+    constexpr int G = 2;  // panel row tiles updated together
     __shared__ PotrfSmem smem[IPB];
     const int lane = threadIdx.x & 63;
     const int inst = threadIdx.x >> 6;
@@ -166,70 +213,84 @@ __global__ __launch_bounds__(IPB * 64) void potrf_lower_kernel(PotrfArgs p)
         S.fail = INT_MAX;
     wave_lds_sync();
 
-    for (int J = 0; J < NT; ++J) {
-        // 1-3. diagonal tile: update with the factored columns, then factor it
-        d4 t = load_tile(A, lda, n, J, J, lr, lg, true);
-#pragma unroll 2
-        for (int K = 0; K < J; ++K) {
-            const d4 lj = load_tile(A, lda, n, J, K, lr, lg, false);
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-                t = mfma16(-lj[s], lj[s], t);
+    // Block columns are taken two at a time (J and J1 = J + 1): every factored
+    // tile L(I,K) loaded for the update then serves both columns.
+    for (int J = 0; J < NT; J += 2) {
+        const bool two = J + 1 < NT;
+        const int J1 = J + 1;
+        // --- the 2x2 diagonal block: tiles (J,J), (J1,J), (J1,J1) ---
+        d4 t00 = load_tile(A, lda, n, J, J, lr, lg, true);
+        d4 t10 = d4{0.0, 0.0, 0.0, 0.0}, t11 = d4{0.0, 0.0, 0.0, 0.0};
+        if (two) {
+            t10 = load_tile(A, lda, n, J1, J, lr, lg, false);
+            t11 = load_tile(A, lda, n, J1, J1, lr, lg, true);
         }
-        d4 x;
-        factor_diag_tile(t, x, S, J, lane);
-        wave_lds_sync();
-        const int fail_col = S.fail;
-        {
-            const int gi = 16 * J + lr;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int gc = 16 * J + lg + 4 * r;
-                if (gi < n && gc <= gi && gc < fail_col)
-                    A[(size_t)gi + (size_t)gc * lda] = t[r];
+        for (int K = 0; K < J; ++K) {
+            const d4 l0 = load_tile(A, lda, n, J, K, lr, lg, false);
+            t00 = update_nt(t00, l0, l0);
+            if (two) {
+                const d4 l1 = load_tile(A, lda, n, J1, K, lr, lg, false);
+                t10 = update_nt(t10, l1, l0);
+                t11 = update_nt(t11, l1, l1);
             }
         }
-        // 2 + 4. panel tiles, G at a time: update, then L(I,J) = tile * L_JJ^{-T}
-        for (int I0 = J + 1; I0 < NT; I0 += G) {
-            d4 acc[G];
+        d4 w0, w1 = d4{0.0, 0.0, 0.0, 0.0};
+        factor_diag_tile(t00, w0, S, J, lane);
+        wave_lds_sync();
+        int fail_col = S.fail;
+        store_diag(A, lda, n, J, t00, fail_col, lr, lg);
+        d4 l10 = d4{0.0, 0.0, 0.0, 0.0};
+        if (two) {
+            l10 = solve_right(t10, w0);
+            store_tile(A, lda, n, J1, J, l10, fail_col, lr, lg);
+            if (fail_col == INT_MAX) {
+                t11 = update_nt(t11, l10, l10);
+                factor_diag_tile(t11, w1, S, J1, lane);
+                wave_lds_sync();
+                fail_col = S.fail;
+                store_diag(A, lda, n, J1, t11, fail_col, lr, lg);
+            }
+        }
+        // --- panel rows I > J1, G at a time, both columns ---
+        for (int I0 = J + 2; I0 < NT; I0 += G) {
+            d4 a0[G], a1[G];
 #pragma unroll
-            for (int g = 0; g < G; ++g)
-                acc[g] = (I0 + g < NT) ? load_tile(A, lda, n, I0 + g, J, lr, lg, false)
-                                       : d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
+            for (int g = 0; g < G; ++g) {
+                const bool in = I0 + g < NT;
+                a0[g] = in ? load_tile(A, lda, n, I0 + g, J, lr, lg, false) : d4{0.0, 0.0, 0.0, 0.0};
+                a1[g] = (in && two) ? load_tile(A, lda, n, I0 + g, J1, lr, lg, false)
+                                    : d4{0.0, 0.0, 0.0, 0.0};
+            }
             for (int K = 0; K < J; ++K) {
-                const d4 lj = load_tile(A, lda, n, J, K, lr, lg, false);
+                const d4 l0 = load_tile(A, lda, n, J, K, lr, lg, false);
+                const d4 l1 = two ? load_tile(A, lda, n, J1, K, lr, lg, false)
+                                  : d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
                     if (I0 + g < NT) {
                         const d4 li = load_tile(A, lda, n, I0 + g, K, lr, lg, false);
-#pragma unroll
-                        for (int s = 0; s < 4; ++s)
-                            acc[g] = mfma16(-lj[s], li[s], acc[g]);
+                        a0[g] = update_nt(a0[g], li, l0);
+                        if (two)
+                            a1[g] = update_nt(a1[g], li, l1);
                     }
                 }
             }
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 if (I0 + g < NT) {
-                    d4 xo = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        xo = mfma16(x[s], acc[g][s], xo);
-                    const int gi = 16 * (I0 + g) + lr;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int gc = 16 * J + lg + 4 * r;
-                        if (gi < n && gc < n && gc < fail_col)
-                            A[(size_t)gi + (size_t)gc * lda] = xo[r];
+                    const d4 x0 = solve_right(a0[g], w0);
+                    store_tile(A, lda, n, I0 + g, J, x0, fail_col, lr, lg);
+                    if (two) {
+                        const d4 x1 = solve_right(update_nt(a1[g], x0, l10), w1);
+                        store_tile(A, lda, n, I0 + g, J1, x1, fail_col, lr, lg);
                     }
                 }
             }
         }
-        if (fail_col != INT_MAX || J == NT - 1)
+        if (fail_col != INT_MAX || J + 2 >= NT)
             break;
-        // the next steps read this block column back: make the stores visible
-        // to this wave's later loads (complete them, drop stale L1 lines)
+        // the next steps read these block columns back: make the stores
+        // visible to this wave's later loads (complete them, drop stale L1)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
