@@ -133,6 +133,10 @@ int mb_dgemm_strided_batched_config(char transa, char transb, int m, int n, int 
 int mb_dgemm_config_count(void);
 /* Static name of a packed configuration ("illegal" when out of range). */
 const char *mb_dgemm_config_name(int config);
+/* Largest m and n a packed configuration accepts (INT_MAX for the workgroup
+ * tile shapes; a one-wave-per-instance shape holds the whole result), -1 for
+ * an out-of-range configuration. */
+int mb_dgemm_config_max_mn(int config);
 
 /* Host-only query: the kernel family (MB_VARIANT_DIRECT or MB_VARIANT_PACKED)
  * that the plain calls select for this shape, or -1 for an illegal trans. */

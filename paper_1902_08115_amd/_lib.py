@@ -21,7 +21,7 @@ VARIANT_AUTO, VARIANT_DIRECT, VARIANT_PACKED = 0, 1, 2
 EXPORTS = (
     "mb_dgemm", "mb_dgemm_strided_batched", "mb_dgemm_batched",
     "mb_dgemm_strided_batched_ex", "mb_dgemm_batched_ex", "mb_dgemm_strided_batched_config",
-    "mb_dgemm_config_count", "mb_dgemm_config_name", "mb_dgemm_select",
+    "mb_dgemm_config_count", "mb_dgemm_config_name", "mb_dgemm_config_max_mn", "mb_dgemm_select",
     "mb_dgemm_kernel_name", "mb_dpotrf", "mb_dpotrf_strided_batched", "mb_dpotrf_batched",
     "mb_dpotrf_kernel_name",
     "mb_status_string", "mb_version",
@@ -62,6 +62,7 @@ def _load():
     lib.mb_dgemm_strided_batched_config.argtypes = lib.mb_dgemm_strided_batched_ex.argtypes
     lib.mb_dgemm_config_count.argtypes = []
     lib.mb_dgemm_config_name.argtypes = [c_int]
+    lib.mb_dgemm_config_max_mn.argtypes = [c_int]
     lib.mb_dgemm_select.argtypes = [c_char, c_char, c_int, c_int, c_int]
     lib.mb_dpotrf.argtypes = [c_char, c_int, vp, c_int, vp, vp]
     lib.mb_dpotrf_strided_batched.argtypes = [c_char, c_int, vp, c_int, c_i64, vp, c_int, vp]
@@ -124,6 +125,10 @@ def dgemm_config_count() -> int:
 
 def dgemm_config_name(config) -> str:
     return lib.mb_dgemm_config_name(int(config)).decode()
+
+
+def dgemm_config_max_mn(config) -> int:
+    return lib.mb_dgemm_config_max_mn(int(config))
 
 
 def dgemm_select(transa, transb, m, n, k) -> int:

@@ -26,7 +26,6 @@ import time
 SIZES = (4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 300)
 CLASS_MAX = (4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 320, 1 << 30)
 TRANS = ("NN", "NT", "TN", "TT")
-WAVE_LIMIT = {"gemm_packed_wave16": 16, "gemm_packed_wave32": 32, "gemm_packed_wave48": 48}
 
 
 def log(msg):
@@ -88,6 +87,7 @@ def main():
     sh = torch.cuda.current_stream().cuda_stream
     ncfg = _lib.dgemm_config_count()
     names = [_lib.dgemm_config_name(c) for c in range(ncfg)]
+    limit = [_lib.dgemm_config_max_mn(c) for c in range(ncfg)]
     results = []
     best = {t: {} for t in TRANS}
     for n in sizes:
@@ -97,8 +97,7 @@ def main():
         C = inputs.torch_colmajor(batch, n, n, seed=13)
         pa, pb, pc = A.data_ptr(), B.data_ptr(), C.data_ptr()
         for t in TRANS:
-            cands = [("direct", None)] + [(names[c], c) for c in range(ncfg)
-                                          if WAVE_LIMIT.get(names[c], 1 << 30) >= n]
+            cands = [("direct", None)] + [(names[c], c) for c in range(ncfg) if limit[c] >= n]
             timings = {}
             for name, cfg in cands:
                 if cfg is None:
@@ -132,7 +131,7 @@ def main():
             inside = [n for n in best[t] if n <= cm]
             n = max(inside) if inside else min(best[t])
             v, c = best[t][n]
-            if cm > 320 and v == 2 and names[c] in WAVE_LIMIT:
+            if cm > 320 and v == 2 and limit[c] < (1 << 30):
                 c = names.index("gemm_packed_tile64_k16")
             row.append((v, c))
         table[t] = row

@@ -23,9 +23,13 @@ ARCH = os.environ.get("MB_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops off: no packed FP32 instructions are generated anywhere.
+# amdgpu-mfma-vgpr-form: MFMA accumulators live in ordinary VGPRs; otherwise
+# loop-carried accumulators are copied to AGPRs and back around every k-panel,
+# which drains the matrix-core pipeline once per iteration.
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function",
 ]
 

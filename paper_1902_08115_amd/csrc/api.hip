@@ -246,6 +246,14 @@ int mb_dgemm_config_count(void) { return mb::packed_config_count(); }
 
 const char *mb_dgemm_config_name(int config) { return mb::packed_config_name(config); }
 
+int mb_dgemm_config_max_mn(int config)
+{
+    if (config < 0 || config >= mb::packed_config_count())
+        return -1;
+    const int lim = mb::packed_config_wave_limit(config);
+    return lim > 0 ? lim : INT_MAX;
+}
+
 int mb_dgemm_batched(char transa, char transb, int m, int n, int k, double alpha,
                      const double *const *Aarray, int lda, const double *const *Barray, int ldb,
                      double beta, double *const *Carray, int ldc, int batch, hipStream_t stream)

@@ -13,10 +13,10 @@ constexpr int kGemmTuneEntries = 14;
 constexpr int kGemmTuneMaxDim[kGemmTuneEntries] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 320, 1 << 30};
 // {variant, packed configuration} per trans case and size class
 constexpr int kGemmTune[4][kGemmTuneEntries][2] = {
-    {{1, -1}, {1, -1}, {2, 0}, {2, 0}, {2, 1}, {2, 1}, {2, 2}, {2, 3}, {2, 11}, {2, 8}, {2, 4}, {2, 9}, {2, 4}, {2, 4}},
-    {{1, -1}, {1, -1}, {2, 0}, {2, 0}, {2, 1}, {2, 1}, {2, 2}, {2, 3}, {2, 11}, {2, 8}, {2, 5}, {2, 8}, {2, 5}, {2, 5}},
-    {{1, -1}, {2, 0}, {2, 0}, {2, 0}, {2, 1}, {2, 1}, {2, 2}, {2, 3}, {2, 11}, {2, 3}, {2, 3}, {2, 10}, {2, 5}, {2, 5}},
-    {{1, -1}, {2, 0}, {2, 0}, {2, 0}, {2, 1}, {2, 1}, {2, 2}, {2, 3}, {2, 11}, {2, 9}, {2, 4}, {2, 9}, {2, 4}, {2, 4}},
+    {{1, -1}, {1, -1}, {2, 0}, {2, 0}, {2, 1}, {2, 1}, {2, 2}, {2, 4}, {2, 6}, {2, 3}, {2, 3}, {2, 3}, {2, 5}, {2, 5}},
+    {{1, -1}, {1, -1}, {2, 0}, {2, 0}, {2, 1}, {2, 1}, {2, 2}, {2, 3}, {2, 6}, {2, 3}, {2, 3}, {2, 5}, {2, 5}, {2, 5}},
+    {{1, -1}, {2, 0}, {2, 0}, {2, 0}, {2, 1}, {2, 1}, {2, 2}, {2, 3}, {2, 6}, {2, 3}, {2, 3}, {2, 10}, {2, 5}, {2, 5}},
+    {{1, -1}, {2, 0}, {2, 0}, {2, 0}, {2, 1}, {2, 1}, {2, 2}, {2, 3}, {2, 6}, {2, 3}, {2, 3}, {2, 5}, {2, 5}, {2, 5}},
 };
 
 }  // namespace mb

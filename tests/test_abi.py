@@ -136,3 +136,20 @@ def test_kernel_name_queries(L):
     assert L.dgemm_kernel_name("x", "N", 4, 4, 4) == "illegal"
     assert L.dpotrf_kernel_name(256) == "potrf_nt16"
     assert L.dpotrf_kernel_name(400) == "unsupported"
+
+
+def test_config_menu_queries(L):
+    count = L.dgemm_config_count()
+    assert count >= 1
+    names = [L.dgemm_config_name(c) for c in range(count)]
+    assert len(set(names)) == count and all(n.startswith("gemm_packed_") for n in names)
+    assert L.dgemm_config_name(count) == "illegal" and L.dgemm_config_max_mn(count) == -1
+    for c in range(count):
+        lim = L.dgemm_config_max_mn(c)
+        assert lim >= 16
+        if lim < 2 ** 31 - 1:  # a one-wave shape refuses larger instances (host check only)
+            assert L.dgemm_strided_batched_config("N", "N", lim + 1, 1, 1, 1.0, P, lim + 1, 0, P,
+                                                  1, 0, 0.0, P, lim + 1, 0, 1, c) == \
+                L.MB_ERR_UNSUPPORTED
+    assert L.dgemm_strided_batched_config("N", "N", 4, 4, 4, 1.0, P, 4, 16, P, 4, 16, 1.0, P, 4,
+                                          16, 1, count) == -18

@@ -243,8 +243,7 @@ def test_every_packed_config_exact():
     g = inputs.rng(7500)
     for cfg in range(_lib.dgemm_config_count()):
         name = _lib.dgemm_config_name(cfg)
-        lim = {"gemm_packed_wave16": 16, "gemm_packed_wave32": 32, "gemm_packed_wave48": 48}.get(
-            name, 300)
+        lim = min(300, _lib.dgemm_config_max_mn(cfg))
         shapes = [(min(lim, 13), min(lim, 9), 37), (lim, lim, 16), (min(lim, 150), min(lim, 70), 45)]
         for trans in TRANS:
             ta, tb = trans
