@@ -29,12 +29,14 @@
  *     before anything is launched; an illegal call launches nothing, writes
  *     nothing and prints nothing.
  *   - Memory: every matrix, pointer array and info array is caller-owned
- *     DEVICE memory.  No call allocates device or host memory, and no call
- *     synchronizes: work is enqueued on `stream` (0 = null stream) and results
- *     are valid once that stream has completed it.
+ *     DEVICE memory.  Apart from plan creation and destruction (mb_plan_*),
+ *     no call allocates device or host memory, and no call synchronizes: work
+ *     is enqueued on `stream` (0 = null stream) and results are valid once
+ *     that stream has completed it.
  *   - Numerical failure of dpotrf is reported only through the device array
  *     info[] (LAPACK convention), readable after the stream completes.
- *   - Calls are reentrant: the library keeps no mutable global state.
+ *   - Calls are reentrant: the library keeps no mutable global state (a plan
+ *     is state owned by its caller; see mb_plan_create).
  *   - Aliasing: C must not overlap A or B, and distinct batch instances of C
  *     (or of A in dpotrf) must not overlap; otherwise results are undefined.
  *     Input strides (strideA, strideB of dgemm) may be 0 (broadcast).
@@ -52,6 +54,7 @@ extern "C" {
 #define MB_OK 0
 #define MB_ERR_HIP (-1000)
 #define MB_ERR_UNSUPPORTED (-1001)
+#define MB_ERR_INVALID_PROBLEM (-1002) /* a plan problem failed validation */
 
 /* Kernel family selection for the *_ex calls. */
 #define MB_VARIANT_AUTO 0   /* measured size switch (what the plain calls use) */
@@ -177,6 +180,94 @@ int mb_dpotrf_batched(char uplo, int n, double *const *Aarray, int lda, int *inf
 
 /* Host-only query: static name of the kernel class used for order n. */
 const char *mb_dpotrf_kernel_name(int n);
+
+/* ------------------------------------------------------ uneven batches --- */
+
+/*
+ * A batch of independent dgemm and dpotrf problems whose shapes all differ,
+ * run by one persistent kernel.  The paper tunes one routine call at a time
+ * and switches kernel variants by operand size (Sec. 2.4); it leaves batching
+ * aside.  A plan applies the same size switch per problem: each dgemm is cut
+ * into register tiles of one or two 16 x 16 MFMA blocks per side (chosen by
+ * size), each dpotrf is one unit, units are ordered by a measured cost model
+ * (longest first) and dealt to one work queue per XCD, and the persistent
+ * grid drains the queues with atomic counters.  The launch is captured once
+ * in a HIP graph.
+ */
+#define MB_OP_DGEMM 0
+#define MB_OP_DPOTRF 1
+
+/*
+ * One problem.  Every pointer is caller-owned DEVICE memory that must stay
+ * valid (and must not be freed or moved) for the lifetime of the plan.
+ *   dgemm  (op = MB_OP_DGEMM): C <= alpha*op(A)*op(B) + beta*C with the
+ *          semantics, argument rules and quick returns of mb_dgemm; uplo and
+ *          info are ignored.
+ *   dpotrf (op = MB_OP_DPOTRF): the n x n matrix at C (leading dimension ldc)
+ *          is factored in place as by mb_dpotrf('L'); *info receives the
+ *          LAPACK info.  uplo must be 'L'/'l' ('U' is MB_ERR_UNSUPPORTED),
+ *          n <= 304; transa, transb, m, k, alpha, beta, A, B are ignored.
+ * Every operand must span less than 4 GiB (MB_ERR_UNSUPPORTED otherwise).
+ * Problems must not overlap each other's outputs.
+ */
+typedef struct mb_problem {
+    int op;
+    char transa, transb, uplo, reserved;
+    int m, n, k;
+    int lda, ldb, ldc;
+    double alpha, beta;
+    const double *A;
+    const double *B;
+    double *C;
+    int *info;
+} mb_problem;
+
+typedef struct mb_plan mb_plan;
+
+/*
+ * Validate `problems` (host array of `count` >= 0 descriptors, read only
+ * during the call), build the work queues in device memory on the current
+ * device and capture the persistent launch in a HIP graph.  Allocates device
+ * memory and synchronizes the device; *plan receives the handle.
+ * Returns MB_OK; -1 (problems NULL with count > 0), -2 (count < 0), -3 (plan
+ * NULL); MB_ERR_INVALID_PROBLEM or MB_ERR_UNSUPPORTED for the first failing
+ * problem, whose index is stored to *bad_index when bad_index is not NULL;
+ * MB_ERR_HIP.  Nothing is allocated when an error is returned.
+ */
+int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
+                   int64_t *bad_index);
+
+/* Execution modes of mb_plan_execute_mode. */
+#define MB_PLAN_FUSED_GRAPH 0   /* the captured persistent launch (mb_plan_execute) */
+#define MB_PLAN_FUSED 1         /* the same two kernels launched directly          */
+#define MB_PLAN_GROUPED 2       /* one pointer-array batched call per distinct     */
+                                /* (op, trans, m, n, k, ld, alpha, beta) group     */
+#define MB_PLAN_GROUPED_GRAPH 3 /* the grouped calls captured in a HIP graph      */
+                                /* (captured at first use)                         */
+
+/*
+ * Run every problem of the plan on `stream` (enqueue only; no
+ * synchronization).  Executions of one plan share its queue counters, so
+ * they must be ordered (for example issued on one stream); the plan's device
+ * must be current.  The grouped modes exist as the per-shape comparison for
+ * the fused launch and give the same results (bitwise for dpotrf; dgemm
+ * within rounding, the tile code differs).
+ * Returns MB_OK, -1 (plan NULL), -2 (unknown mode), MB_ERR_HIP.
+ */
+int mb_plan_execute(mb_plan *plan, hipStream_t stream);
+int mb_plan_execute_mode(mb_plan *plan, int mode, hipStream_t stream);
+
+/*
+ * Host-only statistics: out[i] for i < n (n <= 8) is
+ *   0 problems, 1 work units, 2 dgemm groups, 3 dpotrf groups,
+ *   4 persistent workgroups, 5 waves per CU, 6 problems with no work
+ *   (quick returns), 7 total estimated cost in nanoseconds of wave time.
+ * Returns MB_OK, -1 (plan NULL), -2 (out NULL with n > 0).
+ */
+int mb_plan_stats(const mb_plan *plan, int64_t *out, int n);
+
+/* Wait for the plan's device, then free everything it owns.  NULL is a no-op. */
+int mb_plan_destroy(mb_plan *plan);
 
 /* ---------------------------------------------------------------- misc --- */
 

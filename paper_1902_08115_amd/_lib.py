@@ -15,7 +15,12 @@ LIB_PATH = os.environ.get("MB_LIBRARY", os.path.join(_HERE, "lib", "libmi355blas
 MB_OK = 0
 MB_ERR_HIP = -1000
 MB_ERR_UNSUPPORTED = -1001
+MB_ERR_INVALID_PROBLEM = -1002
 VARIANT_AUTO, VARIANT_DIRECT, VARIANT_PACKED = 0, 1, 2
+OP_DGEMM, OP_DPOTRF = 0, 1
+PLAN_FUSED_GRAPH, PLAN_FUSED, PLAN_GROUPED, PLAN_GROUPED_GRAPH = 0, 1, 2, 3
+PLAN_STATS = ("problems", "units", "gemm_groups", "potrf_groups", "workgroups", "waves_per_cu",
+              "idle", "cost_ns")
 
 # every symbol the header declares, in declaration order
 EXPORTS = (
@@ -24,8 +29,24 @@ EXPORTS = (
     "mb_dgemm_config_count", "mb_dgemm_config_name", "mb_dgemm_config_max_mn", "mb_dgemm_select",
     "mb_dgemm_kernel_name", "mb_dpotrf", "mb_dpotrf_strided_batched", "mb_dpotrf_batched",
     "mb_dpotrf_kernel_name",
+    "mb_plan_create", "mb_plan_execute", "mb_plan_execute_mode", "mb_plan_stats",
+    "mb_plan_destroy",
     "mb_status_string", "mb_version",
 )
+
+
+class Problem(ctypes.Structure):
+    """struct mb_problem (one problem of an uneven batch; device pointers)."""
+    _fields_ = [
+        ("op", ctypes.c_int),
+        ("transa", ctypes.c_char), ("transb", ctypes.c_char), ("uplo", ctypes.c_char),
+        ("reserved", ctypes.c_char),
+        ("m", ctypes.c_int), ("n", ctypes.c_int), ("k", ctypes.c_int),
+        ("lda", ctypes.c_int), ("ldb", ctypes.c_int), ("ldc", ctypes.c_int),
+        ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+        ("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
+        ("info", ctypes.c_void_p),
+    ]
 
 
 _STRING_FNS = ("mb_status_string", "mb_dgemm_kernel_name", "mb_dpotrf_kernel_name",
@@ -71,6 +92,11 @@ def _load():
     lib.mb_dgemm_kernel_name.argtypes = [c_char, c_char, c_int, c_int, c_int, c_int]
     lib.mb_dpotrf_kernel_name.argtypes = [c_int]
     lib.mb_version.argtypes = []
+    lib.mb_plan_create.argtypes = [vp, c_i64, ctypes.POINTER(vp), ctypes.POINTER(c_i64)]
+    lib.mb_plan_execute.argtypes = [vp, vp]
+    lib.mb_plan_execute_mode.argtypes = [vp, c_int, vp]
+    lib.mb_plan_stats.argtypes = [vp, ctypes.POINTER(c_i64), c_int]
+    lib.mb_plan_destroy.argtypes = [vp]
     for name in EXPORTS:
         getattr(lib, name).restype = ctypes.c_char_p if name in _STRING_FNS else c_int
     return lib
@@ -157,3 +183,52 @@ def dpotrf_batched(uplo, n, Aarr, lda, info, batch, stream=0) -> int:
 
 def version() -> int:
     return lib.mb_version()
+
+
+def problems_array(problems):
+    """ctypes array of Problem from a sequence of Problem or of dicts."""
+    arr = (Problem * len(problems))()
+    for i, p in enumerate(problems):
+        if isinstance(p, Problem):
+            arr[i] = p
+            continue
+        q = arr[i]
+        q.op = int(p.get("op", OP_DGEMM))
+        q.transa = _ch(p.get("transa", "N"))
+        q.transb = _ch(p.get("transb", "N"))
+        q.uplo = _ch(p.get("uplo", "L"))
+        for f in ("m", "n", "k", "lda", "ldb", "ldc"):
+            setattr(q, f, int(p.get(f, 0)))
+        q.alpha = float(p.get("alpha", 1.0))
+        q.beta = float(p.get("beta", 0.0))
+        for f in ("A", "B", "C", "info"):
+            setattr(q, f, p.get(f) or None)
+    return arr
+
+
+def plan_create(problems):
+    """(status, handle or None, bad_index) for a ctypes Problem array."""
+    h = ctypes.c_void_p()
+    bad = ctypes.c_int64(-1)
+    n = len(problems)
+    st = lib.mb_plan_create(ctypes.cast(problems, ctypes.c_void_p) if n else None, n,
+                            ctypes.byref(h), ctypes.byref(bad))
+    return st, (h.value if st == MB_OK else None), bad.value
+
+
+def plan_execute(plan, stream=0, mode=None) -> int:
+    if mode is None:
+        return lib.mb_plan_execute(plan, stream)
+    return lib.mb_plan_execute_mode(plan, int(mode), stream)
+
+
+def plan_stats(plan) -> dict:
+    out = (ctypes.c_int64 * len(PLAN_STATS))()
+    st = lib.mb_plan_stats(plan, out, len(PLAN_STATS))
+    if st != MB_OK:
+        raise MbError("mb_plan_stats", st)
+    return dict(zip(PLAN_STATS, list(out)))
+
+
+def plan_destroy(plan) -> int:
+    return lib.mb_plan_destroy(plan)

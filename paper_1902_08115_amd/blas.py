@@ -9,6 +9,8 @@ caller's back: a tensor in any other layout raises.  ``colmajor_empty`` and
 """
 from __future__ import annotations
 
+import ctypes
+
 import torch
 
 from . import _lib
@@ -134,3 +136,44 @@ def dpotrf_batched(Aptr, n, lda, batch, info=None, stream=None):
                              _stream(stream))
     _raise("mb_dpotrf_batched", st)
     return info
+
+
+class Plan:
+    """An uneven batch of dgemm / dpotrf problems run by one persistent kernel.
+
+    ``problems`` is a sequence of dicts with the fields of struct mb_problem
+    (device addresses as ints: A, B, C, info).  The plan records the
+    addresses: the memory behind them must stay allocated while the plan
+    lives.  ``execute`` enqueues on the current (or given) stream."""
+
+    FUSED_GRAPH, FUSED, GROUPED, GROUPED_GRAPH = (_lib.PLAN_FUSED_GRAPH, _lib.PLAN_FUSED,
+                                                  _lib.PLAN_GROUPED, _lib.PLAN_GROUPED_GRAPH)
+
+    def __init__(self, problems):
+        arr = problems if isinstance(problems, ctypes.Array) else _lib.problems_array(problems)
+        st, self._h, bad = _lib.plan_create(arr)
+        if st != _lib.MB_OK:
+            raise MbError(f"mb_plan_create (problem {bad})", st)
+
+    def execute(self, mode=None, stream=None):
+        _raise("mb_plan_execute", _lib.plan_execute(self._h, _stream(stream), mode))
+
+    def stats(self) -> dict:
+        return _lib.plan_stats(self._h)
+
+    def close(self):
+        if self._h is not None:
+            st = _lib.plan_destroy(self._h)
+            self._h = None
+            _raise("mb_plan_destroy", st)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.plan_destroy(self._h)
+            self._h = None

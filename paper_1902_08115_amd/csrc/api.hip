@@ -93,23 +93,6 @@ int check_gemm(char transa, char transb, int m, int n, int k, int lda, int ldb, 
     return MB_OK;
 }
 
-// variant: MB_VARIANT_*; config >= 0 forces a packed configuration.
-int run_gemm(int ta, int tb, GemmArgs &a, int variant, int config, hipStream_t s)
-{
-    if (a.m == 0 || a.n == 0 || a.batch == 0)
-        return MB_OK;
-    if ((a.alpha == 0.0 || a.k == 0) && a.beta == 1.0)
-        return MB_OK;
-    if (a.alpha == 0.0 || a.k == 0)
-        return to_status(mb::launch_gemm_scale(a, s));
-    if (config >= 0)
-        return to_status(mb::launch_gemm_packed_config(config, ta, tb, a, s));
-    const Choice c = select(ta, tb, a.m, a.n, a.k, variant);
-    if (c.variant == MB_VARIANT_DIRECT)
-        return to_status(mb::launch_gemm_direct(ta, tb, a, s));
-    return to_status(mb::launch_gemm_packed_config(c.config, ta, tb, a, s));
-}
-
 int gemm_strided(char transa, char transb, int m, int n, int k, double alpha, const double *A,
                  int lda, int64_t strideA, const double *B, int ldb, int64_t strideB, double beta,
                  double *C, int ldc, int64_t strideC, int batch, int variant, int pos_variant,
@@ -137,7 +120,7 @@ int gemm_strided(char transa, char transb, int m, int n, int k, double alpha, co
     a.B = B; a.sB = strideB; a.ldb = ldb;
     a.C = C; a.sC = strideC; a.ldc = ldc;
     a.batch = batch;
-    return run_gemm(trans_code(transa), trans_code(transb), a, variant, config, stream);
+    return mb::run_gemm(trans_code(transa), trans_code(transb), a, variant, config, stream);
 }
 
 int gemm_array(char transa, char transb, int m, int n, int k, double alpha,
@@ -163,7 +146,7 @@ int gemm_array(char transa, char transb, int m, int n, int k, double alpha,
     a.Barr = Barray; a.ldb = ldb;
     a.Carr = Carray; a.ldc = ldc;
     a.batch = batch;
-    return run_gemm(trans_code(transa), trans_code(transb), a, variant, -1, stream);
+    return mb::run_gemm(trans_code(transa), trans_code(transb), a, variant, -1, stream);
 }
 
 int uplo_check(char uplo)  // 0 lower, 1 upper (unsupported), -1 illegal
@@ -175,6 +158,27 @@ int uplo_check(char uplo)  // 0 lower, 1 upper (unsupported), -1 illegal
     }
 }
 
+}  // namespace
+
+namespace mb {
+
+// variant: MB_VARIANT_*; config >= 0 forces a packed configuration.
+int run_gemm(int ta, int tb, GemmArgs &a, int variant, int config, hipStream_t s)
+{
+    if (a.m == 0 || a.n == 0 || a.batch == 0)
+        return MB_OK;
+    if ((a.alpha == 0.0 || a.k == 0) && a.beta == 1.0)
+        return MB_OK;
+    if (a.alpha == 0.0 || a.k == 0)
+        return to_status(mb::launch_gemm_scale(a, s));
+    if (config >= 0)
+        return to_status(mb::launch_gemm_packed_config(config, ta, tb, a, s));
+    const Choice c = select(ta, tb, a.m, a.n, a.k, variant);
+    if (c.variant == MB_VARIANT_DIRECT)
+        return to_status(mb::launch_gemm_direct(ta, tb, a, s));
+    return to_status(mb::launch_gemm_packed_config(c.config, ta, tb, a, s));
+}
+
 int run_potrf(PotrfArgs &a, hipStream_t s)
 {
     if (a.batch == 0)
@@ -184,7 +188,7 @@ int run_potrf(PotrfArgs &a, hipStream_t s)
     return to_status(mb::launch_potrf_lower(a, s));
 }
 
-}  // namespace
+}  // namespace mb
 
 extern "C" {
 
@@ -206,7 +210,7 @@ int mb_dgemm(char transa, char transb, int m, int n, int k, double alpha, const 
     a.m = m; a.n = n; a.k = k; a.alpha = alpha; a.beta = beta;
     a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.C = C; a.ldc = ldc;
     a.batch = 1;
-    return run_gemm(trans_code(transa), trans_code(transb), a, MB_VARIANT_AUTO, -1, stream);
+    return mb::run_gemm(trans_code(transa), trans_code(transb), a, MB_VARIANT_AUTO, -1, stream);
 }
 
 int mb_dgemm_strided_batched(char transa, char transb, int m, int n, int k, double alpha,
@@ -313,7 +317,7 @@ int mb_dpotrf(char uplo, int n, double *A, int lda, int *info, hipStream_t strea
     if (!info) return -5;
     PotrfArgs a{};
     a.n = n; a.A = A; a.lda = lda; a.info = info; a.batch = 1;
-    return run_potrf(a, stream);
+    return mb::run_potrf(a, stream);
 }
 
 int mb_dpotrf_strided_batched(char uplo, int n, double *A, int lda, int64_t strideA, int *info,
@@ -332,7 +336,7 @@ int mb_dpotrf_strided_batched(char uplo, int n, double *A, int lda, int64_t stri
     if (batch > 0 && !info) return -6;
     PotrfArgs a{};
     a.n = n; a.A = A; a.sA = strideA; a.lda = lda; a.info = info; a.batch = batch;
-    return run_potrf(a, stream);
+    return mb::run_potrf(a, stream);
 }
 
 int mb_dpotrf_batched(char uplo, int n, double *const *Aarray, int lda, int *info, int batch,
@@ -349,7 +353,7 @@ int mb_dpotrf_batched(char uplo, int n, double *const *Aarray, int lda, int *inf
     if (batch > 0 && !info) return -5;
     PotrfArgs a{};
     a.n = n; a.Aarr = Aarray; a.lda = lda; a.info = info; a.batch = batch;
-    return run_potrf(a, stream);
+    return mb::run_potrf(a, stream);
 }
 
 const char *mb_status_string(int status)
@@ -357,6 +361,7 @@ const char *mb_status_string(int status)
     if (status == MB_OK) return "success";
     if (status == MB_ERR_HIP) return "HIP runtime or launch failure";
     if (status == MB_ERR_UNSUPPORTED) return "unsupported argument combination";
+    if (status == MB_ERR_INVALID_PROBLEM) return "a plan problem failed validation";
     if (status < 0 && status > -64) return "illegal value of argument -status";
     return "unknown status";
 }

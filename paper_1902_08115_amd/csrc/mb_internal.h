@@ -40,6 +40,48 @@ struct PotrfArgs {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// Pointers known to address global memory.  Addresses that reach a kernel
+// through memory (descriptor tables) are generic to the compiler, which then
+// emits flat instructions; casting them keeps the global forms (scalar base +
+// vector offset, no LDS-counter waits).
+#define MB_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ MB_GLOBAL T *global_ptr(T *p)
+{
+    return (MB_GLOBAL T *)p;
+}
+
+// One problem of a fused uneven batch (plan.hip builds these, fused.hip runs
+// them).  kind < FUSED_POTRF: dgemm with trans code (kind & 3) = 2*ta + tb
+// and register tile of TM = 1 + ((kind >> 2) & 1) by TN = 1 + (kind >> 3)
+// 16 x 16 MFMA tiles; tiles_m = ceil(m / (16 TM)).  alpha == 0 or k == 0 is
+// stored as alpha = 0, k = 0 (C = beta C).  kind == FUSED_POTRF: lower
+// Cholesky of the n x n matrix at C (leading dimension ldc), info to *info.
+struct FusedDesc {
+    const double *A, *B;
+    double *C;
+    int *info;
+    double alpha, beta;
+    int m, n, k;
+    int lda, ldb, ldc;
+    int kind, tiles_m;
+};
+constexpr int FUSED_POTRF = 16;
+constexpr int FUSED_QUEUES = 8;      // one work queue per XCD
+constexpr int FUSED_CTR_STRIDE = 32;  // ints between queue counters (128 B)
+
+// One unit of work: problem index and linear tile index (tile_m + tile_n * tiles_m).
+struct FusedUnit {
+    uint32_t prob, tile;
+};
+
+struct FusedArgs {
+    const FusedDesc *desc;
+    const FusedUnit *units;
+    const int *qoff;  // FUSED_QUEUES + 1 offsets into units
+    int *counters;    // FUSED_QUEUES counters, FUSED_CTR_STRIDE apart
+};
+
 __device__ __forceinline__ const double *inst_ptr(const double *base, const double *const *arr,
                                                   int64_t stride, int64_t b)
 {
@@ -100,6 +142,16 @@ hipError_t launch_fill_info(int *info, int batch, hipStream_t s);
 int packed_config_count();
 const char *packed_config_name(int config);
 int packed_config_wave_limit(int config);  // > 0: largest m, n of a WAVE shape; 0: any
+
+// Fused persistent batch (fused.hip).
+hipError_t launch_fused(const FusedArgs &a, int grid, hipStream_t s);
+hipError_t fused_grid(int *grid, int *waves_per_cu);  // persistent grid for the current device
+hipError_t launch_scatter_info(const int *src, int *const *dst, int count, hipStream_t s);
+
+// Validated dgemm / dpotrf launches used by the C ABI and by plans (api.hip):
+// quick returns, size-class dispatch, launch.  Return an MB_ status.
+int run_gemm(int ta, int tb, GemmArgs &a, int variant, int config, hipStream_t s);
+int run_potrf(PotrfArgs &a, hipStream_t s);
 
 // Name of the potrf kernel class for order n (profiling attribution).
 const char *potrf_kernel_name(int n);

@@ -1,0 +1,301 @@
+// potrf_wave.h -- one wave factors one lower Cholesky instance (dpotrf 'L').
+//
+// Shared by the batched kernel (potrf.hip) and the fused persistent kernel
+// (fused.hip).  The paper builds LAPACK routines as nested loops around
+// tailored kernels rather than on top of BLAS calls (Sec. 1, Sec. 3.1), with
+// the factorization kernel composed of the shared dgemm_nt rank-k inner loop,
+// a subtraction (alpha = -1, beta = 1), a register-resident factorization of
+// the diagonal block and a lower-triangle store (Sec. 3.2.1); off-diagonal
+// blocks use the right-variant triangular solve, which vectorizes across rows
+// (Sec. 3.1.3).
+//
+// gfx950 design: blocked in 16 x 16 tiles (the FP64 MFMA tile) and
+// left-looking, so only a few tiles live in the wave's registers and many
+// instances share a CU (their serial pivot chains hide behind each other's
+// matrix-core work).  Tiles are held in accumulator order -- lane (g, i),
+// register r holds element (16I + i, 16J + g + 4r).  With PAIR, block columns
+// are processed two at a time, so every factored tile loaded for the update
+// serves both (half the re-reads of the factor, more registers).  For one
+// block column J:
+//   1. tile(J,J) of A minus L(J,K) * L(J,K)^T for every factored block column
+//      K < J: four MFMA steps per K whose operands are the registers s of
+//      L(J,K) loaded from the factor already written (the k index of step s in
+//      lane group g is g + 4s: the accumulator order itself, so no reshuffle);
+//   2. factor the diagonal tile in registers and form L_JJ^{-1} alongside
+//      (inner_edge_dpotrf); write the lower part of L_JJ;
+//   3. panel tiles I > J, two at a time: tile(I,J) of A minus
+//      L(I,K) * L(J,K)^T for K < J (the dgemm_nt inner update, alpha = -1,
+//      beta = 1), then L(I,J) = tile(I,J) * L_JJ^{-T}, four MFMA steps with
+//      L_JJ^{-1} (also in accumulator order) as the left operand -- the
+//      right-variant solve expressed as a product with the inverted diagonal
+//      block; write L(I,J).
+// Only the lower triangle is read or written.  Orders that are not a multiple
+// of 16 are padded with the identity, which the factorization leaves
+// unchanged.  The first non-positive (or NaN) pivot stops the instance and is
+// reported as info = column + 1 (LAPACK).
+#pragma once
+
+#include <limits.h>
+
+#include "mb_internal.h"
+
+namespace mb {
+
+// Per-wave LDS for broadcasting the column being eliminated in the diagonal
+// tile (double-buffered by column parity).
+struct PotrfSmem {
+    double col[2][16];   // column being eliminated (diagonal tile)
+    double xrow[2][16];  // row of L^{-1} being propagated (diagonal tile)
+    int fail;            // first failing global column, INT_MAX if none
+};
+
+// Factor one 16x16 diagonal tile held in accumulator order -- lane (g, i),
+// register r holds T[i][g + 4r] -- by one whole wave (inner_edge_dpotrf).
+// Column c is eliminated in step c: its current values are published through
+// LDS, every lane forms l_ic = T[i][c]/l_cc for its row and l_qc for its four
+// columns q, and updates its own entries T[i][q] -= l_ic*l_qc (c < q <= i).
+// Alongside, X = L^{-1} is accumulated in the same order as the product of
+// inverted column factors (X <= C_c^{-1} X with C_c the identity except for
+// column c of L): row c is scaled by 1/l_cc and rows i > c lose l_ic times it.
+// Row c of X is published with column c+1 of T, so each step costs a single
+// LDS round trip.  A failing pivot at column c is recorded in S.fail; columns
+// c..15 are then replaced by the identity so that L stays invertible.
+// On exit t holds L (upper part zero) and x holds L^{-1}, both in accumulator
+// order -- which is exactly the left-operand order the panel MFMA needs.
+template <class Smem>
+__device__ __forceinline__ void factor_diag_tile(d4 &t, d4 &x, Smem &S, int J, int lane)
+{
+    const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        x[r] = (i == g + 4 * r) ? 1.0 : 0.0;
+    bool failed = false;
+    double lic_prev = 0.0;  // l_{i,c-1} of the previous step
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const int buf = c & 1;
+        // publish column c of T and (from step 1 on) the scaled row c-1 of X
+        if (g == (c & 3))
+            S.col[buf][i] = t[c >> 2];
+        if (c > 0 && i == c - 1) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                S.xrow[buf][g + 4 * r] = x[r];
+        }
+        wave_lds_sync();
+        // X update of step c-1: rows i > c-1 lose l_{i,c-1} * (scaled row c-1)
+        if (c > 0 && i > c - 1) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                x[r] = fma(-lic_prev, S.xrow[buf][g + 4 * r], x[r]);
+        }
+        const double piv = S.col[buf][c];
+        if (!failed && !(piv > 0.0)) {
+            failed = true;  // uniform: every lane read the same pivot
+            if (lane == 0)
+                S.fail = 16 * J + c;
+        }
+        double ljj = 1.0, rinv = 1.0;
+        if (!failed) {
+            ljj = sqrt(piv);
+            rinv = 1.0 / ljj;
+        }
+        // l_ic for this lane's row (zero above the diagonal and after a failure)
+        double lic;
+        if (i == c)
+            lic = ljj;
+        else if (i > c && !failed)
+            lic = S.col[buf][i] * rinv;
+        else
+            lic = 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int q = g + 4 * r;
+            if (q > c && q <= i && !failed)
+                t[r] = fma(-lic, S.col[buf][q] * rinv, t[r]);
+        }
+        if (g == (c & 3))
+            t[c >> 2] = (i >= c) ? lic : 0.0;
+        if (i == c) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                x[r] *= rinv;
+        }
+        lic_prev = (i > c) ? lic : 0.0;
+    }
+    // zero the strict upper part of L (entries of T never touched above)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (g + 4 * r > i)
+            t[r] = 0.0;
+}
+
+// Load tile (I, K) in accumulator order.  diag: the tile of A on the
+// diagonal (strict upper part read as zero); outside the n x n matrix the
+// identity is used.
+__device__ __forceinline__ d4 load_tile(const MB_GLOBAL double *A, size_t lda, int n, int I, int K,
+                                        int lr, int lg, bool diag)
+{
+    d4 t;
+    const int gi = 16 * I + lr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int gc = 16 * K + lg + 4 * r;
+        double v = 0.0;
+        if (gi < n && gc < n) {
+            if (!diag || gi >= gc)
+                v = A[(size_t)gi + (size_t)gc * lda];
+        } else if (gi == gc) {
+            v = 1.0;
+        }
+        t[r] = v;
+    }
+    return t;
+}
+
+// Store the lower part of a diagonal tile (columns before a failing pivot).
+__device__ __forceinline__ void store_diag(MB_GLOBAL double *A, size_t lda, int n, int J, const d4 &t,
+                                           int fail_col, int lr, int lg)
+{
+    const int gi = 16 * J + lr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int gc = 16 * J + lg + 4 * r;
+        if (gi < n && gc <= gi && gc < fail_col)
+            A[(size_t)gi + (size_t)gc * lda] = t[r];
+    }
+}
+
+// Store an off-diagonal tile (I, J) of L (columns before a failing pivot).
+__device__ __forceinline__ void store_tile(MB_GLOBAL double *A, size_t lda, int n, int I, int J, const d4 &t,
+                                           int fail_col, int lr, int lg)
+{
+    const int gi = 16 * I + lr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int gc = 16 * J + lg + 4 * r;
+        if (gi < n && gc < n && gc < fail_col)
+            A[(size_t)gi + (size_t)gc * lda] = t[r];
+    }
+}
+
+// tile * W^T with W = L_JJ^{-1} in accumulator order (the right-variant solve).
+__device__ __forceinline__ d4 solve_right(const d4 &tile, const d4 &w)
+{
+    d4 xo = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        xo = mfma16(w[s], tile[s], xo);
+    return xo;
+}
+
+// acc -= X * Y^T for two tiles in accumulator order.
+__device__ __forceinline__ d4 update_nt(d4 acc, const d4 &x, const d4 &y)
+{
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        acc = mfma16(-y[s], x[s], acc);
+    return acc;
+}
+
+// Factor the n x n lower triangle of A (nt = ceil(n / 16) tiles) with the
+// calling wave; returns the LAPACK info (0, or the failing column + 1).  S is
+// this wave's private LDS block.
+template <bool PAIR>
+__device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT, PotrfSmem &S,
+                                          int lane)
+{
+    MB_GLOBAL double *A = global_ptr(Ain);
+    constexpr int G = 2;  // panel row tiles updated together
+    const int lr = lane & 15, lg = lane >> 4;
+    constexpr int STEP = PAIR ? 2 : 1;
+    if (lane == 0)
+        S.fail = INT_MAX;
+    wave_lds_sync();
+
+    // With PAIR block columns are taken two at a time (J and J1 = J + 1):
+    // every factored tile L(I,K) loaded for the update then serves both.
+    for (int J = 0; J < NT; J += STEP) {
+        const bool two = PAIR && J + 1 < NT;
+        const int J1 = J + 1;
+        // --- the 2x2 diagonal block: tiles (J,J), (J1,J), (J1,J1) ---
+        d4 t00 = load_tile(A, lda, n, J, J, lr, lg, true);
+        d4 t10 = d4{0.0, 0.0, 0.0, 0.0}, t11 = d4{0.0, 0.0, 0.0, 0.0};
+        if (two) {
+            t10 = load_tile(A, lda, n, J1, J, lr, lg, false);
+            t11 = load_tile(A, lda, n, J1, J1, lr, lg, true);
+        }
+        for (int K = 0; K < J; ++K) {
+            const d4 l0 = load_tile(A, lda, n, J, K, lr, lg, false);
+            t00 = update_nt(t00, l0, l0);
+            if (two) {
+                const d4 l1 = load_tile(A, lda, n, J1, K, lr, lg, false);
+                t10 = update_nt(t10, l1, l0);
+                t11 = update_nt(t11, l1, l1);
+            }
+        }
+        d4 w0, w1 = d4{0.0, 0.0, 0.0, 0.0};
+        factor_diag_tile(t00, w0, S, J, lane);
+        wave_lds_sync();
+        int fail_col = S.fail;
+        store_diag(A, lda, n, J, t00, fail_col, lr, lg);
+        d4 l10 = d4{0.0, 0.0, 0.0, 0.0};
+        if (two) {
+            l10 = solve_right(t10, w0);
+            store_tile(A, lda, n, J1, J, l10, fail_col, lr, lg);
+            if (fail_col == INT_MAX) {
+                t11 = update_nt(t11, l10, l10);
+                factor_diag_tile(t11, w1, S, J1, lane);
+                wave_lds_sync();
+                fail_col = S.fail;
+                store_diag(A, lda, n, J1, t11, fail_col, lr, lg);
+            }
+        }
+        // --- panel rows I > J1, G at a time, both columns ---
+        for (int I0 = J + STEP; I0 < NT; I0 += G) {
+            d4 a0[G], a1[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const bool in = I0 + g < NT;
+                a0[g] = in ? load_tile(A, lda, n, I0 + g, J, lr, lg, false) : d4{0.0, 0.0, 0.0, 0.0};
+                a1[g] = (in && two) ? load_tile(A, lda, n, I0 + g, J1, lr, lg, false)
+                                    : d4{0.0, 0.0, 0.0, 0.0};
+            }
+            for (int K = 0; K < J; ++K) {
+                const d4 l0 = load_tile(A, lda, n, J, K, lr, lg, false);
+                const d4 l1 = two ? load_tile(A, lda, n, J1, K, lr, lg, false)
+                                  : d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    if (I0 + g < NT) {
+                        const d4 li = load_tile(A, lda, n, I0 + g, K, lr, lg, false);
+                        a0[g] = update_nt(a0[g], li, l0);
+                        if (two)
+                            a1[g] = update_nt(a1[g], li, l1);
+                    }
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                if (I0 + g < NT) {
+                    const d4 x0 = solve_right(a0[g], w0);
+                    store_tile(A, lda, n, I0 + g, J, x0, fail_col, lr, lg);
+                    if (two) {
+                        const d4 x1 = solve_right(update_nt(a1[g], x0, l10), w1);
+                        store_tile(A, lda, n, I0 + g, J1, x1, fail_col, lr, lg);
+                    }
+                }
+            }
+        }
+        if (fail_col != INT_MAX || J + STEP >= NT)
+            break;
+        // the next steps read these block columns back: make the stores
+        // visible to this wave's later loads (complete them, drop stale L1)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    return (S.fail == INT_MAX) ? 0 : S.fail + 1;
+}
+
+
+}  // namespace mb

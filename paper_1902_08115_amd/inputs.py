@@ -143,3 +143,98 @@ def torch_spd(batch: int, n: int, seed: int = 0, device="cuda", chunk: int = 512
         out[b0:b1] = S + n * eye
     # symmetric, so the row-major buffer is also the column-major one
     return out.transpose(1, 2)
+
+
+# ----------------------------------------------------------------------------
+# Uneven batch: independent dgemm and dpotrf problems of mixed sizes.
+# ----------------------------------------------------------------------------
+
+UNEVEN_COUNT = 100_000
+UNEVEN_LO, UNEVEN_HI = 4, 160
+UNEVEN_P_GEMM = 0.7
+
+
+def uneven_spec(count: int, seed: int, lo: int = UNEVEN_LO, hi: int = UNEVEN_HI,
+                p_gemm: float = UNEVEN_P_GEMM, non_spd_frac: float = 0.0) -> dict:
+    """Problem list of an uneven batch.
+
+    Each problem is a dgemm with probability p_gemm, else a lower dpotrf.  m,
+    n, k are independent log-uniform draws in [lo, hi] (a dpotrf uses n as its
+    order); transa, transb are 'N'/'T' with probability 1/2 each; alpha =
+    beta = 1.  A fraction non_spd_frac of the dpotrf problems gets one
+    diagonal entry -1 at a seeded column (fail_col >= 0, expected info
+    fail_col + 1); the others have fail_col = -1.
+
+    Every operand is stored tight (ld = rows) in one arena, problem after
+    problem: dgemm A, B, C; dpotrf its n x n matrix (at off_c).  Returns numpy
+    arrays op (0 dgemm, 1 dpotrf), ta, tb, m, n, k, lda, ldb, ldc, off_a,
+    off_b, off_c, fail_col and the arena length `total` (elements)."""
+    g = rng(seed)
+    op = (g.uniform(size=count) >= p_gemm).astype(np.int64)
+    m = log_uniform_sizes(g, count, lo, hi)
+    n = log_uniform_sizes(g, count, lo, hi)
+    k = log_uniform_sizes(g, count, lo, hi)
+    ta = g.integers(0, 2, size=count)
+    tb = g.integers(0, 2, size=count)
+    fail_draw = g.uniform(size=count)
+    fail_pos = g.uniform(size=count)
+    gemm = op == 0
+    lda = np.where(gemm, np.where(ta == 0, m, k), 0)
+    acols = np.where(gemm, np.where(ta == 0, k, m), 0)
+    ldb = np.where(gemm, np.where(tb == 0, k, n), 0)
+    bcols = np.where(gemm, np.where(tb == 0, n, k), 0)
+    ldc = np.where(gemm, m, n)
+    size_a = lda * acols
+    size_b = ldb * bcols
+    size_c = ldc * n
+    ends = np.cumsum(size_a + size_b + size_c)
+    start = ends - (size_a + size_b + size_c)
+    fail_col = np.where((~gemm) & (fail_draw < non_spd_frac),
+                        np.minimum((fail_pos * n).astype(np.int64), n - 1), -1)
+    return dict(op=op, ta=ta, tb=tb, m=m, n=n, k=k, lda=lda, ldb=ldb, ldc=ldc,
+                off_a=start, off_b=start + size_a, off_c=start + size_a + size_b,
+                fail_col=fail_col, total=int(ends[-1]) if count else 0, count=count,
+                alpha=1.0, beta=1.0)
+
+
+def uneven_host(spec: dict, seed: int) -> np.ndarray:
+    """Host arena for ``spec``: uniform [-1, 1) everywhere, then every dpotrf
+    matrix replaced by M M^T + n I (exactly symmetric) and its fail column set."""
+    g = rng(seed)
+    X = g.uniform(-1.0, 1.0, size=spec["total"])
+    for i in np.nonzero(spec["op"] == 1)[0]:
+        n = int(spec["n"][i])
+        S = spd_batch(g, 1, n)[0]  # (n, n) column-major, ld = n
+        o = int(spec["off_c"][i])
+        X[o:o + n * n] = S.ravel()
+        f = int(spec["fail_col"][i])
+        if f >= 0:
+            X[o + f + f * n] = -1.0
+    return X
+
+
+def uneven_device(spec: dict, seed: int, device="cuda"):
+    """Device arena for ``spec`` drawn with torch's seeded generator (the same
+    recipe as ``uneven_host``, different random stream): one flat float64
+    tensor."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    X = torch.empty(spec["total"], dtype=torch.float64, device=device)
+    X.uniform_(-1.0, 1.0, generator=gen)
+    pot = np.nonzero(spec["op"] == 1)[0]
+    sizes = spec["n"][pot]
+    for si, n in enumerate(np.unique(sizes)):
+        n = int(n)
+        idx = pot[sizes == n]
+        S = torch_spd(len(idx), n, seed=int(seed) * 1000 + si, device=device)
+        S = S.transpose(1, 2).reshape(len(idx), n * n)  # symmetric: same bytes either way
+        offs = torch.as_tensor(spec["off_c"][idx], dtype=torch.int64, device=device)
+        flat = (offs[:, None] + torch.arange(n * n, device=device)[None, :]).reshape(-1)
+        X.index_copy_(0, flat, S.reshape(-1))
+    fail = np.nonzero(spec["fail_col"] >= 0)[0]
+    if len(fail):
+        f = spec["fail_col"][fail]
+        pos = spec["off_c"][fail] + f + f * spec["n"][fail]
+        X[torch.as_tensor(pos, dtype=torch.int64, device=device)] = -1.0
+    return X

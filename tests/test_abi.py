@@ -153,3 +153,44 @@ def test_config_menu_queries(L):
                 L.MB_ERR_UNSUPPORTED
     assert L.dgemm_strided_batched_config("N", "N", 4, 4, 4, 1.0, P, 4, 16, P, 4, 16, 1.0, P, 4,
                                           16, 1, count) == -18
+
+
+def test_plan_argument_errors(L):
+    """Plan creation validates everything on the host before touching the
+    device: argument positions, then the first failing problem by index."""
+    import ctypes
+    h = ctypes.c_void_p()
+    bad = ctypes.c_int64(-1)
+    assert L.lib.mb_plan_create(None, 1, ctypes.byref(h), ctypes.byref(bad)) == -1
+    arr = L.problems_array([dict(op=0, m=4, n=4, k=4, lda=4, ldb=4, ldc=4, A=P, B=P, C=P)])
+    assert L.lib.mb_plan_create(ctypes.cast(arr, ctypes.c_void_p), -1, ctypes.byref(h),
+                                ctypes.byref(bad)) == -2
+    assert L.lib.mb_plan_create(ctypes.cast(arr, ctypes.c_void_p), 1, None, None) == -3
+    good = dict(op=0, m=4, n=4, k=4, lda=4, ldb=4, ldc=4, A=P, B=P, C=P)
+    pot = dict(op=1, uplo="L", n=8, ldc=8, C=P, info=P)
+    cases = [
+        (dict(good, op=7), L.MB_ERR_INVALID_PROBLEM),
+        (dict(good, transa="x"), L.MB_ERR_INVALID_PROBLEM),
+        (dict(good, m=-1), L.MB_ERR_INVALID_PROBLEM),
+        (dict(good, lda=3), L.MB_ERR_INVALID_PROBLEM),
+        (dict(good, transb="T", n=6, ldb=5), L.MB_ERR_INVALID_PROBLEM),
+        (dict(good, ldc=3), L.MB_ERR_INVALID_PROBLEM),
+        (dict(good, A=None), L.MB_ERR_INVALID_PROBLEM),
+        (dict(good, C=None), L.MB_ERR_INVALID_PROBLEM),
+        (dict(good, m=70000, n=70000, lda=70000, ldc=70000), L.MB_ERR_UNSUPPORTED),  # > 4 GiB
+        (dict(pot, uplo="U"), L.MB_ERR_UNSUPPORTED),
+        (dict(pot, uplo="q"), L.MB_ERR_INVALID_PROBLEM),
+        (dict(pot, n=305, ldc=305), L.MB_ERR_UNSUPPORTED),
+        (dict(pot, ldc=7), L.MB_ERR_INVALID_PROBLEM),
+        (dict(pot, info=None), L.MB_ERR_INVALID_PROBLEM),
+        (dict(pot, C=None), L.MB_ERR_INVALID_PROBLEM),
+    ]
+    for prob, want in cases:
+        arr = L.problems_array([good, pot, prob])
+        st, handle, idx = L.plan_create(arr)
+        assert (st, idx, handle) == (want, 2, None), (prob, st, idx)
+    assert L.lib.mb_plan_execute(None, None) == -1
+    assert L.lib.mb_plan_execute_mode(None, 0, None) == -1
+    assert L.lib.mb_plan_stats(None, None, 0) == -1
+    assert L.lib.mb_plan_destroy(None) == 0
+    assert "plan problem" in L.status_string(L.MB_ERR_INVALID_PROBLEM)
