@@ -17,6 +17,10 @@ constexpr double kFusedGemmFixedNs = 2500.0;
 constexpr double kFusedGemmMfmaNs = 110.0;
 constexpr double kFusedGemmLoadNs = 50.0;
 constexpr double kFusedPotrfNs[4] = {2000.0, 8000.0, 0.0, 100.0};
+#ifdef FUSED_TWO_MIN
+constexpr int kFusedTwoMin = FUSED_TWO_MIN;
+#else
 constexpr int kFusedTwoMin = 16;
+#endif
 
 }  // namespace mb

@@ -51,34 +51,33 @@ __device__ __forceinline__ MB_GLOBAL T *global_ptr(T *p)
     return (MB_GLOBAL T *)p;
 }
 
-// One problem of a fused uneven batch (plan.hip builds these, fused.hip runs
-// them).  kind < FUSED_POTRF: dgemm with trans code (kind & 3) = 2*ta + tb
-// and register tile of TM = 1 + ((kind >> 2) & 1) by TN = 1 + (kind >> 3)
-// 16 x 16 MFMA tiles; tiles_m = ceil(m / (16 TM)).  alpha == 0 or k == 0 is
-// stored as alpha = 0, k = 0 (C = beta C).  kind == FUSED_POTRF: lower
-// Cholesky of the n x n matrix at C (leading dimension ldc), info to *info.
-struct FusedDesc {
+// One unit of work of a fused uneven batch (plan.hip builds these, fused.hip
+// runs them): a register tile of a dgemm, or a whole dpotrf.
+//   kind < FUSED_POTRF: dgemm with trans code (kind & 3) = 2*ta + tb and a
+//     register tile of TM = 1 + ((kind >> 2) & 1) by TN = 1 + (kind >> 3)
+//     16 x 16 MFMA blocks whose first row / column are i0 / j0.  alpha == 0
+//     or k == 0 is stored as alpha = 0, k = 0 (C = beta C).
+//   kind == FUSED_POTRF: lower Cholesky of the n x n matrix at C (leading
+//     dimension ldc), info to *info.
+// 96 bytes, so that a wave fetches one with a few scalar loads.
+struct FusedTask {
     const double *A, *B;
     double *C;
     int *info;
     double alpha, beta;
     int m, n, k;
     int lda, ldb, ldc;
-    int kind, tiles_m;
+    int kind, i0, j0;
+    int pad[3];
 };
+static_assert(sizeof(FusedTask) == 96, "FusedTask layout");
 constexpr int FUSED_POTRF = 16;
-constexpr int FUSED_QUEUES = 8;      // one work queue per XCD
+constexpr int FUSED_QUEUES = 8;       // one work queue per XCD
 constexpr int FUSED_CTR_STRIDE = 32;  // ints between queue counters (128 B)
 
-// One unit of work: problem index and linear tile index (tile_m + tile_n * tiles_m).
-struct FusedUnit {
-    uint32_t prob, tile;
-};
-
 struct FusedArgs {
-    const FusedDesc *desc;
-    const FusedUnit *units;
-    const int *qoff;  // FUSED_QUEUES + 1 offsets into units
+    const FusedTask *tasks;
+    const int *qoff;  // FUSED_QUEUES + 1 offsets into tasks
     int *counters;    // FUSED_QUEUES counters, FUSED_CTR_STRIDE apart
 };
 

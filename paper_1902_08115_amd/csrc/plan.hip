@@ -16,8 +16,14 @@
 
 namespace {
 
-using mb::FusedDesc;
-using mb::FusedUnit;
+using mb::FusedTask;
+
+// Per problem with work: the task template (i0 = j0 = 0) and its tiling.
+struct ProblemWork {
+    FusedTask t;
+    int tile_rows, tile_cols;  // rows / columns of C per task
+    int64_t tiles_m, tiles_n;
+};
 
 int tcode(char t)
 {
@@ -232,7 +238,7 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
     if (count > (int64_t)UINT32_MAX) return MB_ERR_UNSUPPORTED;
 
     // ---- validate, choose tiles, estimate costs ---------------------------
-    std::vector<FusedDesc> desc;
+    std::vector<ProblemWork> desc;
     std::vector<double> unit_ns;   // per problem with work
     std::vector<uint32_t> nunits;  // per problem with work
     std::vector<int64_t> src;      // problem index of each descriptor
@@ -250,44 +256,48 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
             ++idle;
             continue;
         }
-        FusedDesc d{};
+        ProblemWork w{};
+        FusedTask &d = w.t;
         double ns;
-        uint32_t nu;
+        int64_t nu;
         if (q.op == MB_OP_DGEMM) {
             const int ta = tcode(q.transa), tb = tcode(q.transb);
             const bool scale_only = q.alpha == 0.0 || q.k == 0;
             const int tm = q.m > mb::kFusedTwoMin ? 2 : 1;
             const int tn = q.n > mb::kFusedTwoMin ? 2 : 1;
-            d.A = q.A; d.B = q.B; d.C = q.C; d.info = nullptr;
+            d.A = scale_only ? nullptr : q.A;
+            d.B = scale_only ? nullptr : q.B;
+            d.C = q.C;
             d.alpha = scale_only ? 0.0 : q.alpha;
             d.beta = q.beta;
             d.m = q.m; d.n = q.n; d.k = scale_only ? 0 : q.k;
             d.lda = q.lda; d.ldb = q.ldb; d.ldc = q.ldc;
             d.kind = (2 * ta + tb) | ((tm - 1) << 2) | ((tn - 1) << 3);
-            d.tiles_m = (q.m + 16 * tm - 1) / (16 * tm);
-            const int64_t tiles_n = (q.n + 16 * tn - 1) / (16 * tn);
-            if ((int64_t)d.tiles_m * tiles_n > (int64_t)UINT32_MAX) {
-                if (bad_index) *bad_index = i;
-                return MB_ERR_UNSUPPORTED;
-            }
-            nu = (uint32_t)(d.tiles_m * tiles_n);
+            w.tile_rows = 16 * tm;
+            w.tile_cols = 16 * tn;
+            w.tiles_m = (q.m + w.tile_rows - 1) / w.tile_rows;
+            w.tiles_n = (q.n + w.tile_cols - 1) / w.tile_cols;
+            nu = w.tiles_m * w.tiles_n;
             ns = gemm_unit_ns(tm, tn, d.k);
         } else {
             d.C = q.C; d.info = q.info;
             d.n = q.n; d.ldc = q.ldc;
             d.kind = mb::FUSED_POTRF;
-            d.tiles_m = 1;
+            w.tiles_m = w.tiles_n = 1;
             nu = 1;
             ns = potrf_unit_ns(q.n);
         }
-        desc.push_back(d);
+        if (total_units + nu > (int64_t)INT32_MAX) {
+            if (bad_index) *bad_index = i;
+            return MB_ERR_UNSUPPORTED;
+        }
+        desc.push_back(w);
         unit_ns.push_back(ns);
-        nunits.push_back(nu);
+        nunits.push_back((uint32_t)nu);
         src.push_back(i);
         total_units += nu;
         total_ns += ns * nu;
     }
-    if (total_units > (int64_t)INT32_MAX) return MB_ERR_UNSUPPORTED;
 
     // ---- longest-processing-time order, greedy balance over the queues ----
     const int64_t nd = (int64_t)desc.size();
@@ -304,14 +314,23 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
         load[best] += unit_ns[pi] * nunits[pi];
         qprob[best].push_back(pi);
     }
-    std::vector<FusedUnit> units;
+    // a queue lists its problems in that order, the tiles of one problem
+    // adjacent (column-major over the tile grid) so they share the L2
+    std::vector<FusedTask> units;
     units.reserve((size_t)total_units);
     std::vector<int> qoff(mb::FUSED_QUEUES + 1, 0);
     for (int q = 0; q < mb::FUSED_QUEUES; ++q) {
         qoff[q] = (int)units.size();
-        for (uint32_t pi : qprob[q])
-            for (uint32_t t = 0; t < nunits[pi]; ++t)
-                units.push_back(FusedUnit{pi, t});
+        for (uint32_t pi : qprob[q]) {
+            const ProblemWork &w = desc[pi];
+            for (int64_t tn = 0; tn < w.tiles_n; ++tn)
+                for (int64_t tm = 0; tm < w.tiles_m; ++tm) {
+                    FusedTask t = w.t;
+                    t.i0 = (int)(tm * w.tile_rows);
+                    t.j0 = (int)(tn * w.tile_cols);
+                    units.push_back(t);
+                }
+        }
     }
     qoff[mb::FUSED_QUEUES] = (int)units.size();
 
@@ -375,8 +394,7 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
 
     // ---- device memory: one block ------------------------------------------
     Arena ar;
-    const size_t o_desc = ar.take(sizeof(FusedDesc) * (size_t)nd);
-    const size_t o_units = ar.take(sizeof(FusedUnit) * units.size());
+    const size_t o_units = ar.take(sizeof(FusedTask) * units.size());
     const size_t o_qoff = ar.take(sizeof(int) * qoff.size());
     const size_t o_ctr = ar.take(sizeof(int) * mb::FUSED_QUEUES * mb::FUSED_CTR_STRIDE);
     const size_t o_gA = ar.take(sizeof(void *) * (size_t)nd);
@@ -398,8 +416,7 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
         const void *src;
         size_t bytes;
     } ups[] = {
-        {o_desc, desc.data(), sizeof(FusedDesc) * (size_t)nd},
-        {o_units, units.data(), sizeof(FusedUnit) * units.size()},
+        {o_units, units.data(), sizeof(FusedTask) * units.size()},
         {o_qoff, qoff.data(), sizeof(int) * qoff.size()},
         {o_gA, hA.data(), sizeof(void *) * (size_t)nd},
         {o_gB, hB.data(), sizeof(void *) * (size_t)nd},
@@ -417,8 +434,7 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
         release(p);
         return MB_ERR_HIP;
     }
-    p->args.desc = reinterpret_cast<const FusedDesc *>(b + o_desc);
-    p->args.units = reinterpret_cast<const FusedUnit *>(b + o_units);
+    p->args.tasks = reinterpret_cast<const FusedTask *>(b + o_units);
     p->args.qoff = reinterpret_cast<const int *>(b + o_qoff);
     p->args.counters = reinterpret_cast<int *>(b + o_ctr);
     p->gA = reinterpret_cast<const double **>(b + o_gA);
