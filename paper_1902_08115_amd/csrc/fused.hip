@@ -13,14 +13,13 @@
 //
 // The work is latency-bound per wave, so the loop keeps memory requests in
 // flight at every step: the index of the task after next is claimed, and the
-// next task is fetched (scalar loads, it is wave-uniform), while the current
-// one runs; inside a dgemm tile the operands of k chunk c + 1 are loaded
+// next task is fetched, while the current one runs; inside a dgemm tile the operands of k chunk c + 1 are loaded
 // while the matrix cores work on chunk c.
 //
 // dgemm tasks are TM x TN tiles of 16 x 16 FP64 MFMA blocks computed straight
 // from global memory: within one wave the operand fragments of a 16-deep k
-// chunk partition the A and B panels exactly (lane (g, i) holds k = kk + 4g +
-// s, s = 0..3, of row i), so there is no redundant load to share through LDS
+// chunk partition the A and B panels exactly (lane (g, i) holds four k of row
+// i, the four lane groups together all 16), so there is no redundant load to share through LDS
 // and no LDS traffic or barrier at all.  As in the batched kernels the MFMA
 // takes op(B) as its left operand and accumulates C^T, so a lane owns whole
 // rows of C and the epilogue stores are coalesced along columns.  dpotrf tasks
@@ -38,19 +37,16 @@ __device__ __forceinline__ const MB_GLOBAL double &at(const double *base, uint32
     return *(const MB_GLOBAL double *)((const MB_GLOBAL char *)global_ptr(base) + byte_off);
 }
 
-// Four consecutive doubles at base + byte_off as two 16-byte loads (the
+// Two consecutive doubles at base + byte_off with one 16-byte load (the
 // address is only known to be 8-byte aligned, which the 16-byte global load
 // form accepts).
 typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
-__device__ __forceinline__ void load4(const double *base, uint32_t byte_off, double (&x)[4])
+__device__ __forceinline__ void load2(const double *base, uint32_t byte_off, double &x0,
+                                      double &x1)
 {
-    const MB_GLOBAL d2u *p =
-        (const MB_GLOBAL d2u *)((const MB_GLOBAL char *)global_ptr(base) + byte_off);
-    const d2u v0 = p[0], v1 = p[1];
-    x[0] = v0.x;
-    x[1] = v0.y;
-    x[2] = v1.x;
-    x[3] = v1.y;
+    const d2u v = *(const MB_GLOBAL d2u *)((const MB_GLOBAL char *)global_ptr(base) + byte_off);
+    x0 = v.x;
+    x1 = v.y;
 }
 
 // One register tile: C(i0:i0+16TM, j0:j0+16TN) <= alpha op(A) op(B) + beta C.
@@ -119,92 +115,123 @@ __device__ __forceinline__ void regtile(const FusedTask &t, int lane)
         for (int tj = 0; tj < TN; ++tj)
             acc[ti][tj] = d4{0.0, 0.0, 0.0, 0.0};
 
-    // Chunk c covers k = 16c + 4 lg + s, s = 0..3, for lane group lg.  The
-    // four k of a lane are consecutive, so an operand stored along k ('T' A,
-    // 'N' B) is read with two 16-byte loads per fragment.  In the last chunk
-    // a group that crosses K starts at K - 4 instead (the order of k inside
-    // a chunk is free as long as A and B agree): its first slots then repeat
-    // k of the previous group and are zeroed, as are groups past K, and no
-    // address ever passes K - 1.  Needs K >= 4; smaller K take the clamped
-    // single-chunk path below.
-    auto group_start = [&](int c) {
-        const int kb = 16 * c + 4 * lg;
-        return kb < K - 4 ? kb : K - 4;
-    };
-    auto load_chunk = [&](int c, double (&xa)[TM][4], double (&xb)[TN][4]) {
-        const uint32_t kg = (uint32_t)group_start(c);
+    // k runs in chunks of 16 with the remainder first: the head chunk covers
+    // k < r = K - 16 (nch - 1), 1 <= r <= 16, and chunk c >= 1 covers
+    // [r + 16 (c - 1), r + 16 c), always full.  In a chunk starting at k0,
+    // slot s of lane group lg holds k = k0 + 8 (s/2) + 2 lg + (s%2): a lane's
+    // slots are two pairs of consecutive k, and the four lane groups of one
+    // row tile a contiguous 64-byte run per pair, so an operand stored along
+    // k ('T' A, 'N' B) is read with one 16-byte load per pair, each load
+    // instruction covering 64 contiguous bytes of every row it touches.  (The
+    // order of k inside a chunk is free as long as A and B agree.)
+    //
+    // In the head, a pair that crosses r starts at r - 2 instead: its first
+    // slot then repeats a k of the previous pair and is zeroed, as are pairs
+    // past r, and no address passes r - 1; when r <= 8 the second pair is
+    // skipped outright (a wave-uniform branch), and r == 1 uses slot 0 of lane
+    // group 0 alone.  (The head's loads and MFMAs sit behind wave-uniform
+    // branches, so the compiler waits for all loads before the head MFMAs;
+    // from chunk 1 on, the loads of the next chunk overlap the MFMAs.)
+    auto load_pair = [&](uint32_t ks, int p, double (&xa)[TM][4], double (&xb)[TN][4]) {
 #pragma unroll
         for (int ti = 0; ti < TM; ++ti) {
             if constexpr (TA) {
-                load4(A, (ra[ti] + kg) * 8u, xa[ti]);
+                load2(A, (ra[ti] + ks) * 8u, xa[ti][2 * p], xa[ti][2 * p + 1]);
             } else {
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    xa[ti][s] = at(A, (ra[ti] + (kg + (uint32_t)s) * lda) * 8u);
+                xa[ti][2 * p] = at(A, (ra[ti] + ks * lda) * 8u);
+                xa[ti][2 * p + 1] = at(A, (ra[ti] + (ks + 1u) * lda) * 8u);
             }
         }
 #pragma unroll
         for (int tj = 0; tj < TN; ++tj) {
             if constexpr (!TB) {
-                load4(B, (rb[tj] + kg) * 8u, xb[tj]);
+                load2(B, (rb[tj] + ks) * 8u, xb[tj][2 * p], xb[tj][2 * p + 1]);
             } else {
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    xb[tj][s] = at(B, (rb[tj] + (kg + (uint32_t)s) * ldb) * 8u);
+                xb[tj][2 * p] = at(B, (rb[tj] + ks * ldb) * 8u);
+                xb[tj][2 * p + 1] = at(B, (rb[tj] + (ks + 1u) * ldb) * 8u);
             }
         }
     };
-    auto mfma_chunk = [&](int c, const double (&xa)[TM][4], const double (&xb)[TN][4]) {
-        const int kb = 16 * c + 4 * lg;
-        const int kg = group_start(c);
+    auto mfma_slot = [&](int s, bool keep, const double (&xa)[TM][4], const double (&xb)[TN][4]) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const bool keep = kg + s >= kb;
-#pragma unroll
-            for (int ti = 0; ti < TM; ++ti)
-#pragma unroll
-                for (int tj = 0; tj < TN; ++tj)
-                    acc[ti][tj] = mfma16(keep ? xb[tj][s] : 0.0, keep ? xa[ti][s] : 0.0,
-                                         acc[ti][tj]);
-        }
-    };
-
-    const int nch = (K + 15) >> 4;
-    if (K >= 4) {
-        double fa[TM][4], fb[TN][4];
-        load_chunk(0, fa, fb);
-        for (int c = 0; c < nch; ++c) {
-            double ga[TM][4], gb[TN][4];
-            load_chunk(c + 1 < nch ? c + 1 : c, ga, gb);  // the last one re-reads (cache hits)
-            mfma_chunk(c, fa, fb);
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-#pragma unroll
-                for (int ti = 0; ti < TM; ++ti)
-                    fa[ti][s] = ga[ti][s];
-#pragma unroll
-                for (int tj = 0; tj < TN; ++tj)
-                    fb[tj][s] = gb[tj][s];
-            }
-        }
-    } else if (K > 0) {
-        // 1 <= K <= 3: one chunk, lane group 0 only, k clamped and zeroed past K
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const bool keep = lg == 0 && s < K;
-            const uint32_t k = (uint32_t)(s < K ? s : K - 1);
-            double xa[TM], xb[TN];
-#pragma unroll
-            for (int ti = 0; ti < TM; ++ti)
-                xa[ti] = at(A, (ra[ti] + k * ska) * 8u);
+        for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
             for (int tj = 0; tj < TN; ++tj)
-                xb[tj] = at(B, (rb[tj] + k * skb) * 8u);
+                acc[ti][tj] = mfma16(keep ? xb[tj][s] : 0.0, keep ? xa[ti][s] : 0.0, acc[ti][tj]);
+    };
+    auto load_full = [&](int c, double (&xa)[TM][4], double (&xb)[TN][4], int r) {
+        const uint32_t k0 = (uint32_t)(r + 16 * (c - 1) + 2 * lg);
+        load_pair(k0, 0, xa, xb);
+        load_pair(k0 + 8u, 1, xa, xb);
+    };
+    auto mfma_full = [&](const double (&xa)[TM][4], const double (&xb)[TN][4]) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            mfma_slot(s, true, xa, xb);
+    };
+    // head pair p: first k and whether slot e of it is new
+    auto head_start = [&](int p, int r) {
+        const int kn = 8 * p + 2 * lg;
+        return kn < r - 2 ? kn : r - 2;
+    };
+
+    if (K == 1) {
+        // one product term: slot 0 of lane group 0
+        double fa[TM][4], fb[TN][4];
+#pragma unroll
+        for (int ti = 0; ti < TM; ++ti)
+            fa[ti][0] = at(A, ra[ti] * 8u);
+#pragma unroll
+        for (int tj = 0; tj < TN; ++tj)
+            fb[tj][0] = at(B, rb[tj] * 8u);
+        mfma_slot(0, lg == 0, fa, fb);
+    } else if (K >= 2) {
+        const int nch = (K + 15) >> 4;
+        const int r = K - 16 * (nch - 1);  // 2 <= r <= 16 unless K = 16 c + 1
+        double fa[TM][4], fb[TN][4], ga[TM][4], gb[TN][4];
+        if (r >= 2) {
+            load_pair((uint32_t)head_start(0, r), 0, fa, fb);
+            if (r > 8)
+                load_pair((uint32_t)head_start(1, r), 1, fa, fb);
+        } else {
 #pragma unroll
             for (int ti = 0; ti < TM; ++ti)
+                fa[ti][0] = at(A, ra[ti] * 8u);  // k = 0
 #pragma unroll
-                for (int tj = 0; tj < TN; ++tj)
-                    acc[ti][tj] = mfma16(keep ? xb[tj] : 0.0, keep ? xa[ti] : 0.0, acc[ti][tj]);
+            for (int tj = 0; tj < TN; ++tj)
+                fb[tj][0] = at(B, rb[tj] * 8u);
+        }
+        if (nch > 1)
+            load_full(1, ga, gb, r);  // in flight during the head's MFMAs
+        if (r >= 2) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+                mfma_slot(s, head_start(0, r) + s >= 2 * lg, fa, fb);
+            if (r > 8) {
+#pragma unroll
+                for (int s = 2; s < 4; ++s)
+                    mfma_slot(s, head_start(1, r) + (s & 1) >= 8 + 2 * lg, fa, fb);
+            }
+        } else {
+            mfma_slot(0, lg == 0, fa, fb);  // k = 0 alone
+        }
+        if (nch > 1) {
+            // chunk c + 1 is loaded before the MFMAs of chunk c
+            for (int c = 2; c < nch; ++c) {
+                double ha[TM][4], hb[TN][4];
+                load_full(c, ha, hb, r);
+                mfma_full(ga, gb);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+#pragma unroll
+                    for (int ti = 0; ti < TM; ++ti)
+                        ga[ti][s] = ha[ti][s];
+#pragma unroll
+                    for (int tj = 0; tj < TN; ++tj)
+                        gb[tj][s] = hb[tj][s];
+                }
+            }
+            mfma_full(ga, gb);
         }
     }
 
@@ -263,7 +290,7 @@ __device__ __forceinline__ void run_task(const FusedTask &t, PotrfSmem &S, int l
 #undef MB_FUSED_CASE
 }
 
-constexpr int FUSED_WAVES = 4;  // waves per workgroup, each an independent worker
+constexpr int FUSED_WAVES = kFusedWaves;  // waves per workgroup, each an independent worker
 
 // Claim the next task of a queue: one atomic per wave, issued by lane 0.  The
 // result stays in lane 0's register until claim_get reads it, so the atomic's
@@ -277,39 +304,86 @@ __device__ __forceinline__ int claim_issue(int *ctr, int lane)
 }
 __device__ __forceinline__ int claim_get(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// The restrict-qualified read-only task table lets the compiler fetch tasks
-// with scalar loads straight into scalar registers.
-__global__ __launch_bounds__(FUSED_WAVES * 64) void fused_kernel(
-    const FusedTask *__restrict__ tasks, const int *__restrict__ qoff, int *counters)
+// A task travels as one vector register: lane w < 24 holds dword w of the
+// 96-byte record (one coalesced load), and the fields are read out with
+// readlane when the task starts.  Two tasks in flight then cost two vector
+// registers instead of 48 scalar ones.
+__device__ __forceinline__ int task_fetch(const FusedTask *tasks, int idx, int lane)
+{
+    const MB_GLOBAL int *p = (const MB_GLOBAL int *)global_ptr(tasks + idx);
+    return lane < 24 ? p[lane] : 0;
+}
+__device__ __forceinline__ uint32_t word(int v, int w)
+{
+    return (uint32_t)__builtin_amdgcn_readlane(v, w);
+}
+__device__ __forceinline__ uint64_t dword2(int v, int w)
+{
+    return (uint64_t)word(v, w) | ((uint64_t)word(v, w + 1) << 32);
+}
+__device__ __forceinline__ FusedTask task_unpack(int v)
+{
+    FusedTask t;
+    t.A = (const double *)dword2(v, 0);
+    t.B = (const double *)dword2(v, 2);
+    t.C = (double *)dword2(v, 4);
+    t.info = (int *)dword2(v, 6);
+    t.alpha = __builtin_bit_cast(double, dword2(v, 8));
+    t.beta = __builtin_bit_cast(double, dword2(v, 10));
+    t.m = (int)word(v, 12);
+    t.n = (int)word(v, 13);
+    t.k = (int)word(v, 14);
+    t.lda = (int)word(v, 15);
+    t.ldb = (int)word(v, 16);
+    t.ldc = (int)word(v, 17);
+    t.kind = (int)word(v, 18);
+    t.i0 = (int)word(v, 19);
+    t.j0 = (int)word(v, 20);
+    return t;
+}
+
+// Queue 2 x + c holds the class-c tasks (c = 0 dpotrf, 1 dgemm) meant for
+// XCD x.  dpotrf tasks are long and latency-bound, dgemm tiles short and
+// bandwidth-bound: the first potrf_waves waves of every workgroup start on
+// the dpotrf class and the others on the dgemm class, so that both kinds run
+// side by side instead of one phase after the other; a wave whose class is
+// drained everywhere moves on to the other class.
+__global__ __launch_bounds__(FUSED_WAVES * 64) void fused_kernel(const FusedTask *tasks,
+                                                                 const int *qoff, int *counters,
+                                                                 int potrf_waves)
 {
     __shared__ PotrfSmem smem[FUSED_WAVES];
     const int lane = threadIdx.x & 63;
-    PotrfSmem &S = smem[threadIdx.x >> 6];
-    const int home = (int)(blockIdx.x % FUSED_QUEUES);  // the XCD this workgroup runs on
-    for (int qi = 0; qi < FUSED_QUEUES; ++qi) {
-        const int q = (home + qi) % FUSED_QUEUES;
-        const int beg = qoff[q], cnt = qoff[q + 1] - beg;
-        int *ctr = counters + q * FUSED_CTR_STRIDE;
-        int u = claim_get(claim_issue(ctr, lane));
-        if (u >= cnt)
-            continue;
-        FusedTask cur = tasks[beg + u];
-        u = claim_get(claim_issue(ctr, lane));
-        for (;;) {
-            // fetch the next task and claim the one after it; both complete
-            // while the current task runs
-            const bool more = u < cnt;
-            FusedTask nxt;
-            int raw = 0;
-            if (more) {
-                nxt = tasks[beg + u];
-                raw = claim_issue(ctr, lane);
+    const int wave = threadIdx.x >> 6;
+    PotrfSmem &S = smem[wave];
+    const int home = (int)(blockIdx.x % FUSED_XCDS);  // the XCD this workgroup runs on
+    const int first = wave < potrf_waves ? 0 : 1;
+    for (int pass = 0; pass < FUSED_CLASSES; ++pass) {
+        const int cls = pass == 0 ? first : 1 - first;
+        for (int xi = 0; xi < FUSED_XCDS; ++xi) {
+            const int q = FUSED_CLASSES * ((home + xi) % FUSED_XCDS) + cls;
+            const int beg = qoff[q], cnt = qoff[q + 1] - beg;
+            int *ctr = counters + q * FUSED_CTR_STRIDE;
+            int u = claim_get(claim_issue(ctr, lane));
+            if (u >= cnt)
+                continue;
+            int cur = task_fetch(tasks, beg + u, lane);
+            u = claim_get(claim_issue(ctr, lane));
+            for (;;) {
+                // fetch the next task and claim the one after it; both
+                // complete while the current task runs
+                const bool more = u < cnt;
+                int nxt = 0, raw = 0;
+                if (more) {
+                    nxt = task_fetch(tasks, beg + u, lane);
+                    raw = claim_issue(ctr, lane);
+                }
+                run_task(task_unpack(cur), S, lane);
+                if (!more)
+                    break;
+                cur = nxt;
+                u = claim_get(raw);
             }
-            run_task(cur, S, lane);
-            if (!more)
-                break;
-            cur = nxt;
-            u = claim_get(raw);
         }
     }
 }
@@ -356,7 +430,7 @@ hipError_t launch_fused(const FusedArgs &a, int grid, hipStream_t s)
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(fused_kernel, dim3((unsigned)grid), dim3(FUSED_WAVES * 64), 0, s, a.tasks,
-                       a.qoff, a.counters);
+                       a.qoff, a.counters, a.potrf_waves);
     return hipGetLastError();
 }
 

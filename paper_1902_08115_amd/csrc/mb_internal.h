@@ -72,13 +72,17 @@ struct FusedTask {
 };
 static_assert(sizeof(FusedTask) == 96, "FusedTask layout");
 constexpr int FUSED_POTRF = 16;
-constexpr int FUSED_QUEUES = 8;       // one work queue per XCD
+constexpr int kFusedWaves = 4;        // waves per workgroup of the fused kernel
+constexpr int FUSED_XCDS = 8;         // XCDs of the device: one queue pair each
+constexpr int FUSED_CLASSES = 2;      // queue class 0: dpotrf, 1: dgemm
+constexpr int FUSED_QUEUES = FUSED_XCDS * FUSED_CLASSES;  // queue 2 x + class
 constexpr int FUSED_CTR_STRIDE = 32;  // ints between queue counters (128 B)
 
 struct FusedArgs {
     const FusedTask *tasks;
     const int *qoff;  // FUSED_QUEUES + 1 offsets into tasks
     int *counters;    // FUSED_QUEUES counters, FUSED_CTR_STRIDE apart
+    int potrf_waves;  // waves per workgroup that start on the dpotrf class
 };
 
 __device__ __forceinline__ const double *inst_ptr(const double *base, const double *const *arr,

@@ -86,7 +86,7 @@ int check_problem(const mb_problem &p, bool *work)
 double gemm_unit_ns(int tm, int tn, int k)
 {
     const int chunks = (k + 15) / 16;
-    return mb::kFusedGemmFixedNs +
+    return mb::kFusedGemmFixedNs + mb::kFusedGemmTileNs * tm * tn +
            chunks * (mb::kFusedGemmMfmaNs * tm * tn + mb::kFusedGemmLoadNs * (tm + tn));
 }
 
@@ -305,14 +305,44 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
     for (int64_t i = 0; i < nd; ++i) order[i] = (uint32_t)i;
     std::stable_sort(order.begin(), order.end(),
                      [&](uint32_t a, uint32_t b) { return unit_ns[a] > unit_ns[b]; });
+    // dpotrf problems: longest first, each to the least-loaded XCD (greedy
+    // LPT); dgemm problems: in address order, cut into one contiguous run per
+    // XCD of equal estimated cost, so that concurrent tiles touch nearby
+    // memory (problem order is arena order for the usual tight layouts).
     std::vector<std::vector<uint32_t>> qprob(mb::FUSED_QUEUES);
-    double load[mb::FUSED_QUEUES] = {};
+    double load[mb::FUSED_XCDS] = {};
+    double gemm_ns = 0.0;
     for (uint32_t pi : order) {
+        if (desc[pi].t.kind != mb::FUSED_POTRF)
+            continue;
         int best = 0;
-        for (int q = 1; q < mb::FUSED_QUEUES; ++q)
-            if (load[q] < load[best]) best = q;
+        for (int x = 1; x < mb::FUSED_XCDS; ++x)
+            if (load[x] < load[best]) best = x;
         load[best] += unit_ns[pi] * nunits[pi];
-        qprob[best].push_back(pi);
+        qprob[mb::FUSED_CLASSES * best + 0].push_back(pi);
+    }
+    for (int64_t i = 0; i < nd; ++i)
+        if (desc[i].t.kind != mb::FUSED_POTRF) gemm_ns += unit_ns[i] * nunits[i];
+    // waves of a workgroup that start on the dpotrf class: in proportion to
+    // its share of the estimated work, at least one while both classes exist
+    int potrf_waves = 0;
+    {
+        const double potrf_ns = total_ns - gemm_ns;
+        if (potrf_ns > 0.0 && gemm_ns <= 0.0) {
+            potrf_waves = mb::kFusedWaves;
+        } else if (potrf_ns > 0.0) {
+            potrf_waves = (int)(mb::kFusedWaves * potrf_ns / total_ns + 0.5);
+            potrf_waves = std::min(std::max(potrf_waves, 1), mb::kFusedWaves - 1);
+        }
+    }
+    double done = 0.0;
+    for (int64_t i = 0; i < nd; ++i) {
+        if (desc[i].t.kind == mb::FUSED_POTRF)
+            continue;
+        int x = gemm_ns > 0.0 ? (int)(done / gemm_ns * mb::FUSED_XCDS) : 0;
+        if (x >= mb::FUSED_XCDS) x = mb::FUSED_XCDS - 1;
+        qprob[mb::FUSED_CLASSES * x + 1].push_back((uint32_t)i);
+        done += unit_ns[i] * nunits[i];
     }
     // a queue lists its problems in that order, the tiles of one problem
     // adjacent (column-major over the tile grid) so they share the L2
@@ -437,6 +467,7 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
     p->args.tasks = reinterpret_cast<const FusedTask *>(b + o_units);
     p->args.qoff = reinterpret_cast<const int *>(b + o_qoff);
     p->args.counters = reinterpret_cast<int *>(b + o_ctr);
+    p->args.potrf_waves = potrf_waves;
     p->gA = reinterpret_cast<const double **>(b + o_gA);
     p->gB = reinterpret_cast<const double **>(b + o_gB);
     p->gC = reinterpret_cast<double **>(b + o_gC);

@@ -201,12 +201,12 @@ __device__ __forceinline__ d4 update_nt(d4 acc, const d4 &x, const d4 &y)
 // Factor the n x n lower triangle of A (nt = ceil(n / 16) tiles) with the
 // calling wave; returns the LAPACK info (0, or the failing column + 1).  S is
 // this wave's private LDS block.
-template <bool PAIR>
+template <bool PAIR, int G = 2>
 __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT, PotrfSmem &S,
                                           int lane)
 {
     MB_GLOBAL double *A = global_ptr(Ain);
-    constexpr int G = 2;  // panel row tiles updated together
+    // G: panel row tiles updated together (register footprint grows with G)
     const int lr = lane & 15, lg = lane >> 4;
     constexpr int STEP = PAIR ? 2 : 1;
     if (lane == 0)
