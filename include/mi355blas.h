@@ -181,6 +181,74 @@ int mb_dpotrf_batched(char uplo, int n, double *const *Aarray, int lda, int *inf
 /* Host-only query: static name of the kernel class used for order n. */
 const char *mb_dpotrf_kernel_name(int n);
 
+/* ------------------------------------------------------------ backward --- */
+
+/*
+ * Reverse-mode derivatives (not in the paper, which has no differentiation;
+ * they are built from its kernels: the dgemm adjoints are dgemm calls with
+ * swapped transposition flags, the Cholesky adjoint uses the right-variant
+ * triangular solve of Sec. 3.1.3 in 16 x 16 MFMA tiles).
+ */
+
+/*
+ * For C = alpha*op(A)*op(B) + beta*C and the cotangent dC of the result:
+ *   dA = alpha * dC * op(B)^T          (transa 'N'; A is m x k)
+ *   dA = alpha * op(B) * dC^T          (transa 'T'; A is k x m)
+ *   dB = alpha * op(A)^T * dC          (transb 'N'; B is k x n)
+ *   dB = alpha * dC^T * op(A)          (transb 'T'; B is n x k)
+ * (the cotangent of the input C is beta*dC and is not formed here).  dA and
+ * dB are overwritten (not accumulated); either may be NULL to skip it.
+ * Strided batches as in mb_dgemm_strided_batched; output strides must keep
+ * instances disjoint.  Arguments: transa 1, transb 2, m 3, n 4, k 5, alpha 6,
+ * A 7, lda 8, strideA 9, B 10, ldb 11, strideB 12, dC 13, lddc (>= max(1,m))
+ * 14, stridedC 15, dA 16, ldda (>= max(1, rows of A)) 17, stridedA 18, dB 19,
+ * lddb (>= max(1, rows of B)) 20, stridedB 21, batch 22, stream 23.
+ * Device memory throughout; dA, dB must not overlap A, B or dC.
+ */
+int mb_dgemm_backward_strided_batched(char transa, char transb, int m, int n, int k, double alpha,
+                                      const double *A, int lda, int64_t strideA, const double *B,
+                                      int ldb, int64_t strideB, const double *dC, int lddc,
+                                      int64_t stridedC, double *dA, int ldda, int64_t stridedA,
+                                      double *dB, int lddb, int64_t stridedB, int batch,
+                                      hipStream_t stream);
+
+/*
+ * Adjoint of the lower Cholesky factorization A = L*L^T: given the factor L
+ * (lower triangle of an n x n array; the strict upper part is never read, so
+ * the array mb_dpotrf wrote can be passed as is) and the cotangent Lbar of L
+ * (lower triangle read), write the symmetric cotangent of A
+ *   Abar = (S + S^T)/2,  S = L^{-T} Phi(L^T Lbar) L^{-1},
+ * Phi taking the lower triangle with the diagonal halved, to all n x n
+ * entries of Abar (the symmetric-gradient convention; <Abar, dA> is the
+ * directional derivative for any symmetric dA).  n <= 304
+ * (MB_ERR_UNSUPPORTED above).  Abar must not overlap L or Lbar; L must be a
+ * successful factorization (nonzero diagonal).
+ * Strided: n 1, L 2, ldl 3, strideL 4, Lbar 5, ldlb 6, strideLbar 7, Abar 8,
+ * ldab 9, strideAbar 10 (>= ldab*(n-1)+n when batch > 1), batch 11, stream 12.
+ * Pointer arrays: n 1, Larray 2, ldl 3, Lbararray 4, ldlb 5, Abararray 6,
+ * ldab 7, batch 8, stream 9.
+ */
+int mb_dpotrf_l_backward_strided_batched(int n, const double *L, int ldl, int64_t strideL,
+                                         const double *Lbar, int ldlb, int64_t strideLbar,
+                                         double *Abar, int ldab, int64_t strideAbar, int batch,
+                                         hipStream_t stream);
+int mb_dpotrf_l_backward_batched(int n, const double *const *Larray, int ldl,
+                                 const double *const *Lbararray, int ldlb,
+                                 double *const *Abararray, int ldab, int batch, hipStream_t stream);
+
+/*
+ * LAPACK dlaset on a batch: the strictly upper ('U'), strictly lower ('L')
+ * or all off-diagonal ('A') elements of each m x n matrix become alpha and
+ * its diagonal beta; used to clear the triangle of a factor that dpotrf
+ * leaves untouched.  Strided: uplo 1, m 2, n 3, alpha 4, beta 5, A 6, lda 7,
+ * strideA 8, batch 9, stream 10.  Pointer arrays: uplo 1, m 2, n 3, alpha 4,
+ * beta 5, Aarray 6, lda 7, batch 8, stream 9.
+ */
+int mb_dlaset_strided_batched(char uplo, int m, int n, double alpha, double beta, double *A,
+                              int lda, int64_t strideA, int batch, hipStream_t stream);
+int mb_dlaset_batched(char uplo, int m, int n, double alpha, double beta, double *const *Aarray,
+                      int lda, int batch, hipStream_t stream);
+
 /* ------------------------------------------------------ uneven batches --- */
 
 /*
@@ -196,6 +264,8 @@ const char *mb_dpotrf_kernel_name(int n);
  */
 #define MB_OP_DGEMM 0
 #define MB_OP_DPOTRF 1
+#define MB_OP_DPOTRF_ADJOINT 2
+#define MB_OP_DLASET 3
 
 /*
  * One problem.  Every pointer is caller-owned DEVICE memory that must stay
@@ -207,6 +277,11 @@ const char *mb_dpotrf_kernel_name(int n);
  *          is factored in place as by mb_dpotrf('L'); *info receives the
  *          LAPACK info.  uplo must be 'L'/'l' ('U' is MB_ERR_UNSUPPORTED),
  *          n <= 304; transa, transb, m, k, alpha, beta, A, B are ignored.
+ *   Cholesky adjoint (op = MB_OP_DPOTRF_ADJOINT): as
+ *          mb_dpotrf_l_backward_strided_batched for one instance, with
+ *          L = A (lda), Lbar = B (ldb), Abar = C (ldc), order n <= 304.
+ *   dlaset (op = MB_OP_DLASET): as mb_dlaset_strided_batched for one m x n
+ *          matrix C (ldc) with uplo, alpha, beta.
  * Every operand must span less than 4 GiB (MB_ERR_UNSUPPORTED otherwise).
  * Problems must not overlap each other's outputs.
  */
@@ -241,7 +316,7 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
 #define MB_PLAN_FUSED_GRAPH 0   /* the captured persistent launch (mb_plan_execute) */
 #define MB_PLAN_FUSED 1         /* the same two kernels launched directly          */
 #define MB_PLAN_GROUPED 2       /* one pointer-array batched call per distinct     */
-                                /* (op, trans, m, n, k, ld, alpha, beta) group     */
+                                /* (op, trans, uplo, m, n, k, ld, alpha, beta)     */
 #define MB_PLAN_GROUPED_GRAPH 3 /* the grouped calls captured in a HIP graph      */
                                 /* (captured at first use)                         */
 
@@ -259,7 +334,7 @@ int mb_plan_execute_mode(mb_plan *plan, int mode, hipStream_t stream);
 
 /*
  * Host-only statistics: out[i] for i < n (n <= 8) is
- *   0 problems, 1 work units, 2 dgemm groups, 3 dpotrf groups,
+ *   0 problems, 1 work units, 2 dgemm groups, 3 groups of the other ops,
  *   4 persistent workgroups, 5 waves per CU, 6 problems with no work
  *   (quick returns), 7 total estimated cost in nanoseconds of wave time.
  * Returns MB_OK, -1 (plan NULL), -2 (out NULL with n > 0).

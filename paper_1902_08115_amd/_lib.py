@@ -17,9 +17,9 @@ MB_ERR_HIP = -1000
 MB_ERR_UNSUPPORTED = -1001
 MB_ERR_INVALID_PROBLEM = -1002
 VARIANT_AUTO, VARIANT_DIRECT, VARIANT_PACKED = 0, 1, 2
-OP_DGEMM, OP_DPOTRF = 0, 1
+OP_DGEMM, OP_DPOTRF, OP_DPOTRF_ADJOINT, OP_DLASET = 0, 1, 2, 3
 PLAN_FUSED_GRAPH, PLAN_FUSED, PLAN_GROUPED, PLAN_GROUPED_GRAPH = 0, 1, 2, 3
-PLAN_STATS = ("problems", "units", "gemm_groups", "potrf_groups", "workgroups", "waves_per_cu",
+PLAN_STATS = ("problems", "units", "gemm_groups", "other_groups", "workgroups", "waves_per_cu",
               "idle", "cost_ns")
 
 # every symbol the header declares, in declaration order
@@ -29,6 +29,8 @@ EXPORTS = (
     "mb_dgemm_config_count", "mb_dgemm_config_name", "mb_dgemm_config_max_mn", "mb_dgemm_select",
     "mb_dgemm_kernel_name", "mb_dpotrf", "mb_dpotrf_strided_batched", "mb_dpotrf_batched",
     "mb_dpotrf_kernel_name",
+    "mb_dgemm_backward_strided_batched", "mb_dpotrf_l_backward_strided_batched",
+    "mb_dpotrf_l_backward_batched", "mb_dlaset_strided_batched", "mb_dlaset_batched",
     "mb_plan_create", "mb_plan_execute", "mb_plan_execute_mode", "mb_plan_stats",
     "mb_plan_destroy",
     "mb_status_string", "mb_version",
@@ -92,6 +94,16 @@ def _load():
     lib.mb_dgemm_kernel_name.argtypes = [c_char, c_char, c_int, c_int, c_int, c_int]
     lib.mb_dpotrf_kernel_name.argtypes = [c_int]
     lib.mb_version.argtypes = []
+    lib.mb_dgemm_backward_strided_batched.argtypes = [
+        c_char, c_char, c_int, c_int, c_int, c_double, vp, c_int, c_i64, vp, c_int, c_i64,
+        vp, c_int, c_i64, vp, c_int, c_i64, vp, c_int, c_i64, c_int, vp]
+    lib.mb_dpotrf_l_backward_strided_batched.argtypes = [c_int, vp, c_int, c_i64, vp, c_int, c_i64,
+                                                         vp, c_int, c_i64, c_int, vp]
+    lib.mb_dpotrf_l_backward_batched.argtypes = [c_int, vp, c_int, vp, c_int, vp, c_int, c_int, vp]
+    lib.mb_dlaset_strided_batched.argtypes = [c_char, c_int, c_int, c_double, c_double, vp, c_int,
+                                              c_i64, c_int, vp]
+    lib.mb_dlaset_batched.argtypes = [c_char, c_int, c_int, c_double, c_double, vp, c_int, c_int,
+                                      vp]
     lib.mb_plan_create.argtypes = [vp, c_i64, ctypes.POINTER(vp), ctypes.POINTER(c_i64)]
     lib.mb_plan_execute.argtypes = [vp, vp]
     lib.mb_plan_execute_mode.argtypes = [vp, c_int, vp]
@@ -179,6 +191,35 @@ def dpotrf_strided_batched(uplo, n, A, lda, sA, info, batch, stream=0) -> int:
 
 def dpotrf_batched(uplo, n, Aarr, lda, info, batch, stream=0) -> int:
     return lib.mb_dpotrf_batched(_ch(uplo), n, Aarr, lda, info, batch, stream)
+
+
+def dgemm_backward_strided_batched(transa, transb, m, n, k, alpha, A, lda, sA, B, ldb, sB, dC,
+                                   lddc, sdC, dA, ldda, sdA, dB, lddb, sdB, batch,
+                                   stream=0) -> int:
+    return lib.mb_dgemm_backward_strided_batched(_ch(transa), _ch(transb), m, n, k, float(alpha),
+                                                 A, lda, sA, B, ldb, sB, dC, lddc, sdC, dA, ldda,
+                                                 sdA, dB, lddb, sdB, batch, stream)
+
+
+def dpotrf_l_backward_strided_batched(n, L, ldl, sL, Lbar, ldlb, sLbar, Abar, ldab, sAbar, batch,
+                                      stream=0) -> int:
+    return lib.mb_dpotrf_l_backward_strided_batched(n, L, ldl, sL, Lbar, ldlb, sLbar, Abar, ldab,
+                                                    sAbar, batch, stream)
+
+
+def dpotrf_l_backward_batched(n, Larr, ldl, Lbararr, ldlb, Abararr, ldab, batch, stream=0) -> int:
+    return lib.mb_dpotrf_l_backward_batched(n, Larr, ldl, Lbararr, ldlb, Abararr, ldab, batch,
+                                            stream)
+
+
+def dlaset_strided_batched(uplo, m, n, alpha, beta, A, lda, sA, batch, stream=0) -> int:
+    return lib.mb_dlaset_strided_batched(_ch(uplo), m, n, float(alpha), float(beta), A, lda, sA,
+                                         batch, stream)
+
+
+def dlaset_batched(uplo, m, n, alpha, beta, Aarr, lda, batch, stream=0) -> int:
+    return lib.mb_dlaset_batched(_ch(uplo), m, n, float(alpha), float(beta), Aarr, lda, batch,
+                                 stream)
 
 
 def version() -> int:

@@ -356,6 +356,171 @@ int mb_dpotrf_batched(char uplo, int n, double *const *Aarray, int lda, int *inf
     return mb::run_potrf(a, stream);
 }
 
+int mb_dgemm_backward_strided_batched(char transa, char transb, int m, int n, int k, double alpha,
+                                      const double *A, int lda, int64_t strideA, const double *B,
+                                      int ldb, int64_t strideB, const double *dC, int lddc,
+                                      int64_t stridedC, double *dA, int ldda, int64_t stridedA,
+                                      double *dB, int lddb, int64_t stridedB, int batch,
+                                      hipStream_t stream)
+{
+    const int ta = trans_code(transa), tb = trans_code(transb);
+    if (ta < 0) return -1;
+    if (tb < 0) return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0) return -5;
+    const int arows = ta ? k : m, acols = ta ? m : k;
+    const int brows = tb ? n : k, bcols = tb ? k : n;
+    if (lda < (arows > 1 ? arows : 1)) return -8;
+    if (strideA < 0) return -9;
+    if (ldb < (brows > 1 ? brows : 1)) return -11;
+    if (strideB < 0) return -12;
+    if (lddc < (m > 1 ? m : 1)) return -14;
+    if (stridedC < 0) return -15;
+    if (ldda < (arows > 1 ? arows : 1)) return -17;
+    if (stridedA < 0 || (dA && batch > 1 && arows > 0 && acols > 0 &&
+                         stridedA < (int64_t)ldda * (acols - 1) + arows))
+        return -18;
+    if (lddb < (brows > 1 ? brows : 1)) return -20;
+    if (stridedB < 0 || (dB && batch > 1 && brows > 0 && bcols > 0 &&
+                         stridedB < (int64_t)lddb * (bcols - 1) + brows))
+        return -21;
+    if (batch < 0) return -22;
+    if (batch == 0)
+        return MB_OK;
+    const bool grad_a = dA && arows > 0 && acols > 0;
+    const bool grad_b = dB && brows > 0 && bcols > 0;
+    const bool reads = alpha != 0.0 && m > 0 && n > 0 && k > 0;
+    if (reads && grad_a && (!dC || !B)) return !dC ? -13 : -10;
+    if (reads && grad_b && (!dC || !A)) return !dC ? -13 : -7;
+    const char nt[2] = {'N', 'T'};
+    int st = MB_OK;
+    // dA = alpha dC op(B)^T ('N' A) or alpha op(B) dC^T ('T' A)
+    if (grad_a) {
+        if (!ta)
+            st = gemm_strided('N', nt[1 - tb], m, k, n, alpha, dC, lddc, stridedC, B, ldb,
+                              strideB, 0.0, dA, ldda, stridedA, batch, MB_VARIANT_AUTO, 0, stream);
+        else
+            st = gemm_strided(nt[tb], 'T', k, m, n, alpha, B, ldb, strideB, dC, lddc, stridedC,
+                              0.0, dA, ldda, stridedA, batch, MB_VARIANT_AUTO, 0, stream);
+        if (st != MB_OK)
+            return st < 0 && st > -64 ? MB_ERR_HIP : st;
+    }
+    // dB = alpha op(A)^T dC ('N' B) or alpha dC^T op(A) ('T' B)
+    if (grad_b) {
+        if (!tb)
+            st = gemm_strided(nt[1 - ta], 'N', k, n, m, alpha, A, lda, strideA, dC, lddc,
+                              stridedC, 0.0, dB, lddb, stridedB, batch, MB_VARIANT_AUTO, 0, stream);
+        else
+            st = gemm_strided('T', nt[ta], n, k, m, alpha, dC, lddc, stridedC, A, lda, strideA,
+                              0.0, dB, lddb, stridedB, batch, MB_VARIANT_AUTO, 0, stream);
+        if (st != MB_OK)
+            return st < 0 && st > -64 ? MB_ERR_HIP : st;
+    }
+    return MB_OK;
+}
+
+int mb_dpotrf_l_backward_strided_batched(int n, const double *L, int ldl, int64_t strideL,
+                                         const double *Lbar, int ldlb, int64_t strideLbar,
+                                         double *Abar, int ldab, int64_t strideAbar, int batch,
+                                         hipStream_t stream)
+{
+    if (n < 0) return -1;
+    if (ldl < (n > 1 ? n : 1)) return -3;
+    if (strideL < 0) return -4;
+    if (ldlb < (n > 1 ? n : 1)) return -6;
+    if (strideLbar < 0) return -7;
+    if (ldab < (n > 1 ? n : 1)) return -9;
+    if (strideAbar < 0 || (batch > 1 && n > 0 && strideAbar < (int64_t)ldab * (n - 1) + n))
+        return -10;
+    if (batch < 0) return -11;
+    if (n > mb::POTRF_MAX_N) return MB_ERR_UNSUPPORTED;
+    if (n == 0 || batch == 0)
+        return MB_OK;
+    if (!L) return -2;
+    if (!Lbar) return -5;
+    if (!Abar) return -8;
+    mb::PotrfAdjArgs a{};
+    a.n = n;
+    a.L = L; a.sL = strideL; a.ldl = ldl;
+    a.Lbar = Lbar; a.sLbar = strideLbar; a.ldlb = ldlb;
+    a.Abar = Abar; a.sAbar = strideAbar; a.ldab = ldab;
+    a.batch = batch;
+    return to_status(mb::launch_potrf_adj(a, stream));
+}
+
+int mb_dpotrf_l_backward_batched(int n, const double *const *Larray, int ldl,
+                                 const double *const *Lbararray, int ldlb,
+                                 double *const *Abararray, int ldab, int batch, hipStream_t stream)
+{
+    if (n < 0) return -1;
+    if (ldl < (n > 1 ? n : 1)) return -3;
+    if (ldlb < (n > 1 ? n : 1)) return -5;
+    if (ldab < (n > 1 ? n : 1)) return -7;
+    if (batch < 0) return -8;
+    if (n > mb::POTRF_MAX_N) return MB_ERR_UNSUPPORTED;
+    if (n == 0 || batch == 0)
+        return MB_OK;
+    if (!Larray) return -2;
+    if (!Lbararray) return -4;
+    if (!Abararray) return -6;
+    mb::PotrfAdjArgs a{};
+    a.n = n;
+    a.Larr = Larray; a.ldl = ldl;
+    a.Lbararr = Lbararray; a.ldlb = ldlb;
+    a.Abararr = Abararray; a.ldab = ldab;
+    a.batch = batch;
+    return to_status(mb::launch_potrf_adj(a, stream));
+}
+
+static int laset_uplo(char u)
+{
+    switch (u) {
+    case 'U': case 'u': return 0;
+    case 'L': case 'l': return 1;
+    case 'A': case 'a': return 2;
+    default: return -1;
+    }
+}
+
+int mb_dlaset_strided_batched(char uplo, int m, int n, double alpha, double beta, double *A,
+                              int lda, int64_t strideA, int batch, hipStream_t stream)
+{
+    const int u = laset_uplo(uplo);
+    if (u < 0) return -1;
+    if (m < 0) return -2;
+    if (n < 0) return -3;
+    if (lda < (m > 1 ? m : 1)) return -7;
+    if (strideA < 0 || (batch > 1 && m > 0 && n > 0 && strideA < (int64_t)lda * (n - 1) + m))
+        return -8;
+    if (batch < 0) return -9;
+    if (m == 0 || n == 0 || batch == 0)
+        return MB_OK;
+    if (!A) return -6;
+    mb::LasetArgs a{};
+    a.uplo = u; a.m = m; a.n = n; a.alpha = alpha; a.beta = beta;
+    a.A = A; a.sA = strideA; a.lda = lda; a.batch = batch;
+    return to_status(mb::launch_laset(a, stream));
+}
+
+int mb_dlaset_batched(char uplo, int m, int n, double alpha, double beta, double *const *Aarray,
+                      int lda, int batch, hipStream_t stream)
+{
+    const int u = laset_uplo(uplo);
+    if (u < 0) return -1;
+    if (m < 0) return -2;
+    if (n < 0) return -3;
+    if (lda < (m > 1 ? m : 1)) return -7;
+    if (batch < 0) return -8;
+    if (m == 0 || n == 0 || batch == 0)
+        return MB_OK;
+    if (!Aarray) return -6;
+    mb::LasetArgs a{};
+    a.uplo = u; a.m = m; a.n = n; a.alpha = alpha; a.beta = beta;
+    a.Aarr = Aarray; a.lda = lda; a.batch = batch;
+    return to_status(mb::launch_laset(a, stream));
+}
+
 const char *mb_status_string(int status)
 {
     if (status == MB_OK) return "success";

@@ -22,8 +22,9 @@
 // i, the four lane groups together all 16), so there is no redundant load to share through LDS
 // and no LDS traffic or barrier at all.  As in the batched kernels the MFMA
 // takes op(B) as its left operand and accumulates C^T, so a lane owns whole
-// rows of C and the epilogue stores are coalesced along columns.  dpotrf tasks
-// run the batched kernel's per-wave factorization.
+// rows of C and the epilogue stores are coalesced along columns.  dpotrf and
+// Cholesky-adjoint tasks run the batched kernels' per-wave routines.
+#include "potrf_adj_wave.h"
 #include "potrf_wave.h"
 
 namespace mb {
@@ -252,8 +253,28 @@ __device__ __forceinline__ void regtile(const FusedTask &t, int lane)
     }
 }
 
+// dlaset on columns [j0, j0 + FUSED_LASET_COLS) of the m x n matrix C; k is
+// the part (0 strictly upper, 1 strictly lower, 2 all off-diagonal).
+__device__ __forceinline__ void laset_task(const FusedTask &t, int lane)
+{
+    MB_GLOBAL double *C = global_ptr(t.C);
+    const int j1 = min(t.j0 + FUSED_LASET_COLS, t.n);
+    for (int j = t.j0; j < j1; ++j)
+        for (int i = lane; i < t.m; i += 64) {
+            const bool sel = i == j || (t.k == 0 ? i < j : (t.k == 1 ? i > j : true));
+            if (sel)
+                C[(size_t)i + (size_t)j * (size_t)t.ldc] = i == j ? t.beta : t.alpha;
+        }
+}
+
+// Per-wave LDS of the dpotrf and Cholesky-adjoint tasks.
+union TaskSmem {
+    PotrfSmem potrf;
+    AdjSmem adj;
+};
+
 // Run one task (kind is wave-uniform).
-__device__ __forceinline__ void run_task(const FusedTask &t, PotrfSmem &S, int lane)
+__device__ __forceinline__ void run_task(const FusedTask &t, TaskSmem &S, int lane)
 {
 #define MB_FUSED_CASE(KIND, TA, TB, TM, TN) \
     case KIND:                              \
@@ -276,14 +297,20 @@ __device__ __forceinline__ void run_task(const FusedTask &t, PotrfSmem &S, int l
         MB_FUSED_CASE(13, false, true, 2, 2)
         MB_FUSED_CASE(14, true, false, 2, 2)
         MB_FUSED_CASE(15, true, true, 2, 2)
-#ifndef FUSED_NO_POTRF
     case FUSED_POTRF: {
-        const int info = potrf_wave<true>(t.C, (size_t)t.ldc, t.n, (t.n + 15) / 16, S, lane);
+        const int info =
+            potrf_wave<true>(t.C, (size_t)t.ldc, t.n, (t.n + 15) / 16, S.potrf, lane);
         if (lane == 0)
             *global_ptr(t.info) = info;
         break;
     }
-#endif
+    case FUSED_POTRF_ADJ:
+        potrf_adj_wave(t.A, (size_t)t.lda, t.B, (size_t)t.ldb, t.C, (size_t)t.ldc, t.n,
+                       (t.n + 15) / 16, S.adj, lane);
+        break;
+    case FUSED_LASET:
+        laset_task(t, lane);
+        break;
     default:
         break;
     }
@@ -352,10 +379,10 @@ __global__ __launch_bounds__(FUSED_WAVES * 64) void fused_kernel(const FusedTask
                                                                  const int *qoff, int *counters,
                                                                  int potrf_waves)
 {
-    __shared__ PotrfSmem smem[FUSED_WAVES];
+    __shared__ TaskSmem smem[FUSED_WAVES];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    PotrfSmem &S = smem[wave];
+    TaskSmem &S = smem[wave];
     const int home = (int)(blockIdx.x % FUSED_XCDS);  // the XCD this workgroup runs on
     const int first = wave < potrf_waves ? 0 : 1;
     for (int pass = 0; pass < FUSED_CLASSES; ++pass) {

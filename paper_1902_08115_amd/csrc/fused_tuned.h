@@ -18,10 +18,8 @@ constexpr double kFusedGemmTileNs = 1800.0;
 constexpr double kFusedGemmMfmaNs = 80.0;
 constexpr double kFusedGemmLoadNs = 50.0;
 constexpr double kFusedPotrfNs[4] = {525.0, 13500.0, -607.0, 144.0};
-#ifdef FUSED_TWO_MIN
-constexpr int kFusedTwoMin = FUSED_TWO_MIN;
-#else
+constexpr double kFusedAdjointNs[4] = {1500.0, 40000.0, 0.0, 450.0};
+constexpr double kFusedLasetNs = 2000.0;
 constexpr int kFusedTwoMin = 16;
-#endif
 
 }  // namespace mb

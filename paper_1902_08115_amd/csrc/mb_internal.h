@@ -38,6 +38,35 @@ struct PotrfArgs {
     int batch;
 };
 
+// One batched Cholesky-adjoint call, already validated.
+struct PotrfAdjArgs {
+    int n;
+    const double *L;
+    const double *const *Larr;
+    int64_t sL;
+    int ldl;
+    const double *Lbar;
+    const double *const *Lbararr;
+    int64_t sLbar;
+    int ldlb;
+    double *Abar;
+    double *const *Abararr;
+    int64_t sAbar;
+    int ldab;
+    int batch;
+};
+
+// One batched dlaset call (uplo 0 = upper, 1 = lower, 2 = all), validated.
+struct LasetArgs {
+    int uplo, m, n;
+    double alpha, beta;
+    double *A;
+    double *const *Aarr;
+    int64_t sA;
+    int lda;
+    int batch;
+};
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // Pointers known to address global memory.  Addresses that reach a kernel
@@ -59,6 +88,7 @@ __device__ __forceinline__ MB_GLOBAL T *global_ptr(T *p)
 //     or k == 0 is stored as alpha = 0, k = 0 (C = beta C).
 //   kind == FUSED_POTRF: lower Cholesky of the n x n matrix at C (leading
 //     dimension ldc), info to *info.
+//   kind == FUSED_POTRF_ADJ, FUSED_LASET: see below.
 // 96 bytes, so that a wave fetches one with a few scalar loads.
 struct FusedTask {
     const double *A, *B;
@@ -72,6 +102,10 @@ struct FusedTask {
 };
 static_assert(sizeof(FusedTask) == 96, "FusedTask layout");
 constexpr int FUSED_POTRF = 16;
+constexpr int FUSED_POTRF_ADJ = 17;  // Cholesky adjoint: A = L, B = Lbar, C = Abar
+constexpr int FUSED_LASET = 18;      // dlaset of columns j0 .. j0 + FUSED_LASET_COLS - 1 of C
+                                     // (k = 0 upper, 1 lower, 2 all)
+constexpr int FUSED_LASET_COLS = 64;
 constexpr int kFusedWaves = 4;        // waves per workgroup of the fused kernel
 constexpr int FUSED_XCDS = 8;         // XCDs of the device: one queue pair each
 constexpr int FUSED_CLASSES = 2;      // queue class 0: dpotrf, 1: dgemm
@@ -140,6 +174,8 @@ hipError_t launch_gemm_packed_config(int config, bool ta, bool tb, const GemmArg
 hipError_t launch_gemm_scale(const GemmArgs &a, hipStream_t s);
 hipError_t launch_potrf_lower(const PotrfArgs &a, hipStream_t s);
 hipError_t launch_fill_info(int *info, int batch, hipStream_t s);
+hipError_t launch_potrf_adj(const PotrfAdjArgs &a, hipStream_t s);
+hipError_t launch_laset(const LasetArgs &a, hipStream_t s);
 
 // The packed configuration menu (gemm_packed.hip).
 int packed_config_count();

@@ -34,6 +34,16 @@ int tcode(char t)
     }
 }
 
+int laset_code(char u)  // 0 upper, 1 lower, 2 all, -1 illegal
+{
+    switch (u) {
+    case 'U': case 'u': return 0;
+    case 'L': case 'l': return 1;
+    case 'A': case 'a': return 2;
+    default: return -1;
+    }
+}
+
 // Elements spanned by a column-major rows x cols operand with leading dimension ld.
 int64_t span(int64_t rows, int64_t cols, int64_t ld)
 {
@@ -62,6 +72,34 @@ int check_problem(const mb_problem &p, bool *work)
             return MB_ERR_INVALID_PROBLEM;
         if (span(arows, acols, p.lda) > kMaxSpan || span(brows, bcols, p.ldb) > kMaxSpan ||
             span(p.m, p.n, p.ldc) > kMaxSpan)
+            return MB_ERR_UNSUPPORTED;
+        *work = true;
+        return MB_OK;
+    }
+    if (p.op == MB_OP_DPOTRF_ADJOINT) {
+        if (p.n < 0 || p.lda < std::max(1, p.n) || p.ldb < std::max(1, p.n) ||
+            p.ldc < std::max(1, p.n))
+            return MB_ERR_INVALID_PROBLEM;
+        if (p.n > mb::POTRF_MAX_N)
+            return MB_ERR_UNSUPPORTED;
+        if (p.n == 0)
+            return MB_OK;
+        if (!p.A || !p.B || !p.C)
+            return MB_ERR_INVALID_PROBLEM;
+        if (span(p.n, p.n, p.lda) > kMaxSpan || span(p.n, p.n, p.ldb) > kMaxSpan ||
+            span(p.n, p.n, p.ldc) > kMaxSpan)
+            return MB_ERR_UNSUPPORTED;
+        *work = true;
+        return MB_OK;
+    }
+    if (p.op == MB_OP_DLASET) {
+        if (laset_code(p.uplo) < 0 || p.m < 0 || p.n < 0 || p.ldc < std::max(1, p.m))
+            return MB_ERR_INVALID_PROBLEM;
+        if (p.m == 0 || p.n == 0)
+            return MB_OK;
+        if (!p.C)
+            return MB_ERR_INVALID_PROBLEM;
+        if (span(p.m, p.n, p.ldc) > kMaxSpan)
             return MB_ERR_UNSUPPORTED;
         *work = true;
         return MB_OK;
@@ -97,6 +135,13 @@ double potrf_unit_ns(int n)
     return c[0] + t * (c[1] + t * (c[2] + t * c[3]));
 }
 
+double adjoint_unit_ns(int n)
+{
+    const double t = (n + 15) / 16;
+    const double *c = mb::kFusedAdjointNs;
+    return c[0] + t * (c[1] + t * (c[2] + t * c[3]));
+}
+
 // Sub-allocation of the plan's single device block.
 struct Arena {
     size_t size = 0;
@@ -129,7 +174,7 @@ struct mb_plan {
     hipGraphExec_t fused_exec = nullptr;
     // grouped execution
     std::vector<PlanGroup> groups;
-    int64_t gemm_groups = 0, potrf_groups = 0;
+    int64_t gemm_groups = 0, other_groups = 0;
     const double **gA = nullptr, **gB = nullptr;
     double **gC = nullptr;
     int *ginfo = nullptr;
@@ -174,11 +219,24 @@ int run_grouped(mb_plan *p, hipStream_t s)
             a.Carr = p->gC + g.off; a.ldc = g.ldc;
             a.batch = (int)g.count;
             st = mb::run_gemm(g.ta, g.tb, a, MB_VARIANT_AUTO, -1, s);
-        } else {
+        } else if (g.op == MB_OP_DPOTRF) {
             mb::PotrfArgs a{};
             a.n = g.n; a.Aarr = p->gC + g.off; a.lda = g.ldc;
             a.info = p->ginfo + g.info_off; a.batch = (int)g.count;
             st = mb::run_potrf(a, s);
+        } else if (g.op == MB_OP_DPOTRF_ADJOINT) {
+            mb::PotrfAdjArgs a{};
+            a.n = g.n;
+            a.Larr = p->gA + g.off; a.ldl = g.lda;
+            a.Lbararr = p->gB + g.off; a.ldlb = g.ldb;
+            a.Abararr = p->gC + g.off; a.ldab = g.ldc;
+            a.batch = (int)g.count;
+            st = to_status(mb::launch_potrf_adj(a, s));
+        } else {
+            mb::LasetArgs a{};
+            a.uplo = g.ta; a.m = g.m; a.n = g.n; a.alpha = g.alpha; a.beta = g.beta;
+            a.Aarr = p->gC + g.off; a.lda = g.ldc; a.batch = (int)g.count;
+            st = to_status(mb::launch_laset(a, s));
         }
         if (st != MB_OK)
             return st;
@@ -279,13 +337,31 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
             w.tiles_n = (q.n + w.tile_cols - 1) / w.tile_cols;
             nu = w.tiles_m * w.tiles_n;
             ns = gemm_unit_ns(tm, tn, d.k);
-        } else {
+        } else if (q.op == MB_OP_DPOTRF) {
             d.C = q.C; d.info = q.info;
             d.n = q.n; d.ldc = q.ldc;
             d.kind = mb::FUSED_POTRF;
             w.tiles_m = w.tiles_n = 1;
             nu = 1;
             ns = potrf_unit_ns(q.n);
+        } else if (q.op == MB_OP_DPOTRF_ADJOINT) {
+            d.A = q.A; d.B = q.B; d.C = q.C;
+            d.n = q.n; d.lda = q.lda; d.ldb = q.ldb; d.ldc = q.ldc;
+            d.kind = mb::FUSED_POTRF_ADJ;
+            w.tiles_m = w.tiles_n = 1;
+            nu = 1;
+            ns = adjoint_unit_ns(q.n);
+        } else {  // MB_OP_DLASET: one task per block of columns
+            d.C = q.C;
+            d.m = q.m; d.n = q.n; d.ldc = q.ldc; d.k = laset_code(q.uplo);
+            d.alpha = q.alpha; d.beta = q.beta;
+            d.kind = mb::FUSED_LASET;
+            w.tile_rows = q.m;
+            w.tile_cols = mb::FUSED_LASET_COLS;
+            w.tiles_m = 1;
+            w.tiles_n = (q.n + w.tile_cols - 1) / w.tile_cols;
+            nu = w.tiles_n;
+            ns = mb::kFusedLasetNs;
         }
         if (total_units + nu > (int64_t)INT32_MAX) {
             if (bad_index) *bad_index = i;
@@ -312,8 +388,11 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
     std::vector<std::vector<uint32_t>> qprob(mb::FUSED_QUEUES);
     double load[mb::FUSED_XCDS] = {};
     double gemm_ns = 0.0;
+    auto long_kind = [&](int64_t i) {
+        return desc[i].t.kind == mb::FUSED_POTRF || desc[i].t.kind == mb::FUSED_POTRF_ADJ;
+    };
     for (uint32_t pi : order) {
-        if (desc[pi].t.kind != mb::FUSED_POTRF)
+        if (!long_kind(pi))
             continue;
         int best = 0;
         for (int x = 1; x < mb::FUSED_XCDS; ++x)
@@ -322,7 +401,7 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
         qprob[mb::FUSED_CLASSES * best + 0].push_back(pi);
     }
     for (int64_t i = 0; i < nd; ++i)
-        if (desc[i].t.kind != mb::FUSED_POTRF) gemm_ns += unit_ns[i] * nunits[i];
+        if (!long_kind(i)) gemm_ns += unit_ns[i] * nunits[i];
     // waves of a workgroup that start on the dpotrf class: in proportion to
     // its share of the estimated work, at least one while both classes exist
     int potrf_waves = 0;
@@ -337,7 +416,7 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
     }
     double done = 0.0;
     for (int64_t i = 0; i < nd; ++i) {
-        if (desc[i].t.kind == mb::FUSED_POTRF)
+        if (long_kind(i))
             continue;
         int x = gemm_ns > 0.0 ? (int)(done / gemm_ns * mb::FUSED_XCDS) : 0;
         if (x >= mb::FUSED_XCDS) x = mb::FUSED_XCDS - 1;
@@ -376,8 +455,14 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
             memcpy(&bb, &q.beta, 8);
             key = Key(0, tcode(q.transa), tcode(q.transb), q.m, q.n, q.k, q.lda, q.ldb, q.ldc,
                       ab, bb);
-        } else {
+        } else if (q.op == MB_OP_DPOTRF) {
             key = Key(1, 0, 0, 0, q.n, 0, 0, 0, q.ldc, 0, 0);
+        } else if (q.op == MB_OP_DPOTRF_ADJOINT) {
+            key = Key(2, 0, 0, 0, q.n, 0, q.lda, q.ldb, q.ldc, 0, 0);
+        } else {
+            memcpy(&ab, &q.alpha, 8);
+            memcpy(&bb, &q.beta, 8);
+            key = Key(3, laset_code(q.uplo), 0, q.m, q.n, 0, 0, 0, q.ldc, ab, bb);
         }
         gmap[key].push_back(src[di]);
     }
@@ -395,7 +480,7 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
     for (const auto &kv : gmap) {
         const Key &k = kv.first;
         PlanGroup g{};
-        g.op = std::get<0>(k) == 0 ? MB_OP_DGEMM : MB_OP_DPOTRF;
+        g.op = std::get<0>(k);  // the MB_OP_ codes
         g.off = off;
         g.count = (int64_t)kv.second.size();
         const mb_problem &q0 = problems[kv.second[0]];
@@ -410,7 +495,7 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
             if (g.op == MB_OP_DPOTRF) hdst.push_back(q.info);
             ++off;
         }
-        if (g.op == MB_OP_DGEMM) ++p->gemm_groups; else ++p->potrf_groups;
+        if (g.op == MB_OP_DGEMM) ++p->gemm_groups; else ++p->other_groups;
         // a batched call takes an int batch count: split larger groups
         for (int64_t start = 0; start < g.count; start += INT32_MAX) {
             PlanGroup part = g;
@@ -521,7 +606,7 @@ int mb_plan_stats(const mb_plan *plan, int64_t *out, int n)
 {
     if (!plan) return -1;
     if (n > 0 && !out) return -2;
-    const int64_t v[8] = {plan->problems, plan->units, plan->gemm_groups, plan->potrf_groups,
+    const int64_t v[8] = {plan->problems, plan->units, plan->gemm_groups, plan->other_groups,
                           plan->grid, plan->waves_per_cu, plan->idle, (int64_t)plan->cost_ns};
     for (int i = 0; i < n && i < 8; ++i)
         out[i] = v[i];

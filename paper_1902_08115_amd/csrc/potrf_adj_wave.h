@@ -1,0 +1,227 @@
+// potrf_adj_wave.h -- one wave computes the reverse-mode derivative of one
+// lower Cholesky factorization.
+//
+// Not in the paper (which has no differentiation); the formula is the
+// standard adjoint of A = L L^T (S. P. Smith 1995; I. Murray 2016):
+//   P = Phi(L^T tril(Lbar))    (lower triangle, diagonal halved)
+//   S = L^{-T} P L^{-1}
+//   Abar = (S + S^T) / 2       (symmetric gradient)
+// computed here with two right-side triangular solves in 16 x 16 FP64 MFMA
+// tiles -- the right-variant solve the paper builds its trsm and Cholesky
+// kernels on (Sec. 3.1.3): Z L = P gives Z = P L^{-1} (lower, since P and
+// L^{-1} are), then W L = Z^T gives W = Z^T L^{-1} = S^T, and
+// Abar = (W + W^T) / 2.  Each solve sweeps the block columns J from the
+// right: tile(I,J) = (rhs(I,J) - sum_{K>J} X(I,K) L(K,J)) L_JJ^{-1}, with
+// L_JJ^{-1} formed in registers (product of inverted column factors) and
+// applied as an MFMA product.  Abar's storage is the workspace: P, then Z,
+// then W overwrite it in an order that never reads a tile after it was
+// replaced.
+//
+// Tiles are in accumulator order (lane (g, i), register r holds element
+// (i, g + 4r) of the tile), as in potrf_wave.h; a transposed tile is loaded
+// by swapping the element coordinates.
+#pragma once
+
+#include "mb_internal.h"
+
+namespace mb {
+
+struct AdjSmem {
+    double col[2][16];   // column being eliminated (inversion), double-buffered
+    double xrow[2][16];  // row of the inverse being propagated
+    double t[16][17];    // tile transpose staging
+};
+
+// The 16 x 16 block M with M[i][c] = X(R0 + i, C0 + c), or X(C0 + c, R0 + i)
+// when trans, in accumulator order.  Elements outside the n x n matrix read
+// 0 (1 on the diagonal when ident); with lower, elements of X above its
+// diagonal read 0.
+__device__ __forceinline__ d4 adj_ld(const MB_GLOBAL double *X, size_t ld, int n, int R0, int C0,
+                                     bool trans, bool lower, bool ident, int lr, int lg)
+{
+    d4 t;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int c = lg + 4 * r;
+        const int row = trans ? C0 + c : R0 + lr;
+        const int col = trans ? R0 + lr : C0 + c;
+        double v;
+        if (row < n && col < n)
+            v = (lower && row < col) ? 0.0 : X[(size_t)row + (size_t)col * ld];
+        else
+            v = (ident && row == col) ? 1.0 : 0.0;
+        t[r] = v;
+    }
+    return t;
+}
+
+// Store M (accumulator order) to X(R0 + i, C0 + c), or X(C0 + c, R0 + i) when
+// trans, inside the n x n matrix only.
+__device__ __forceinline__ void adj_st(MB_GLOBAL double *X, size_t ld, int n, int R0, int C0,
+                                       bool trans, const d4 &t, int lr, int lg)
+{
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int c = lg + 4 * r;
+        const int row = trans ? C0 + c : R0 + lr;
+        const int col = trans ? R0 + lr : C0 + c;
+        if (row < n && col < n)
+            X[(size_t)row + (size_t)col * ld] = t[r];
+    }
+}
+
+// acc + sign * X Y^T for tiles in accumulator order.
+__device__ __forceinline__ d4 adj_xyT(d4 acc, const d4 &x, const d4 &y, double sign)
+{
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        acc = mfma16(sign * y[s], x[s], acc);
+    return acc;
+}
+
+// Inverse of a lower-triangular tile t (accumulator order, nonzero
+// diagonal): X = C_15^{-1} ... C_0^{-1}, where C_c is the identity with
+// column c replaced by column c of t; step c scales row c of X by 1 / t_cc
+// and subtracts t_ic times it from the rows below.  Column c of t and row c
+// of X are broadcast through LDS, one round trip per step.
+__device__ __forceinline__ d4 adj_inv_lower(const d4 &t, AdjSmem &S, int lane)
+{
+    const int i = lane & 15, g = lane >> 4;
+    d4 x;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        x[r] = (i == g + 4 * r) ? 1.0 : 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const int buf = c & 1;
+        if (g == (c & 3))
+            S.col[buf][i] = t[c >> 2];
+        if (i == c) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                S.xrow[buf][g + 4 * r] = x[r];
+        }
+        wave_lds_sync();
+        const double rinv = 1.0 / S.col[buf][c];
+        const double lic = S.col[buf][i];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double xc = S.xrow[buf][g + 4 * r] * rinv;
+            if (i == c)
+                x[r] = xc;
+            else if (i > c)
+                x[r] = fma(-lic, xc, x[r]);
+        }
+    }
+    wave_lds_sync();
+    return x;
+}
+
+// Transpose of a tile in accumulator order, through LDS.
+__device__ __forceinline__ d4 adj_transpose(const d4 &x, AdjSmem &S, int lane)
+{
+    const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        S.t[i][g + 4 * r] = x[r];
+    wave_lds_sync();
+    d4 y;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        y[r] = S.t[g + 4 * r][i];
+    wave_lds_sync();
+    return y;
+}
+
+// Make this wave's global stores visible to its own later loads (complete
+// them, drop stale L1 lines).
+__device__ __forceinline__ void adj_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Abar <= adjoint of the Cholesky factorization at L for the cotangent Lbar
+// (lower triangles of L and Lbar are read; the whole n x n Abar is written).
+// NT = ceil(n / 16).
+__device__ __forceinline__ void potrf_adj_wave(const double *Lp, size_t ldl, const double *Lbp,
+                                               size_t ldlb, double *Ap, size_t lda, int n, int NT,
+                                               AdjSmem &S, int lane)
+{
+    const MB_GLOBAL double *L = global_ptr(Lp);
+    const MB_GLOBAL double *Lb = global_ptr(Lbp);
+    MB_GLOBAL double *Ab = global_ptr(Ap);
+    const int lr = lane & 15, lg = lane >> 4;
+    const d4 zero = d4{0.0, 0.0, 0.0, 0.0};
+
+    // P(I,J) = Phi( sum_{K>=I} L(K,I)^T Lbar(K,J) ), I >= J
+    for (int J = 0; J < NT; ++J) {
+        for (int I = J; I < NT; ++I) {
+            d4 acc = zero;
+            for (int K = I; K < NT; ++K) {
+                const d4 lt = adj_ld(L, ldl, n, 16 * I, 16 * K, true, K == I, false, lr, lg);
+                const d4 bt = adj_ld(Lb, ldlb, n, 16 * J, 16 * K, true, K == J, false, lr, lg);
+                acc = adj_xyT(acc, lt, bt, 1.0);
+            }
+            if (I == J) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = lg + 4 * r;
+                    acc[r] = c > lr ? 0.0 : (c == lr ? 0.5 * acc[r] : acc[r]);
+                }
+            }
+            adj_st(Ab, lda, n, 16 * I, 16 * J, false, acc, lr, lg);
+        }
+    }
+    adj_fence();
+
+    // Z L = P, Z lower: Z(I,J) = (P(I,J) - sum_{J<K<=I} Z(I,K) L(K,J)) L_JJ^{-1}
+    for (int J = NT - 1; J >= 0; --J) {
+        const d4 ljj = adj_ld(L, ldl, n, 16 * J, 16 * J, false, true, true, lr, lg);
+        const d4 winv_t = adj_transpose(adj_inv_lower(ljj, S, lane), S, lane);  // L_JJ^{-T}
+        for (int I = J; I < NT; ++I) {
+            d4 acc = adj_ld(Ab, lda, n, 16 * I, 16 * J, false, false, false, lr, lg);
+            for (int K = J + 1; K <= I; ++K) {
+                const d4 z = adj_ld(Ab, lda, n, 16 * I, 16 * K, false, false, false, lr, lg);
+                const d4 lt = adj_ld(L, ldl, n, 16 * J, 16 * K, true, false, false, lr, lg);
+                acc = adj_xyT(acc, z, lt, -1.0);  // - Z(I,K) L(K,J)
+            }
+            adj_st(Ab, lda, n, 16 * I, 16 * J, false, adj_xyT(zero, acc, winv_t, 1.0), lr, lg);
+        }
+        adj_fence();
+    }
+
+    // W L = Z^T: W(I,J) = (Z(J,I)^T - sum_{K>J} W(I,K) L(K,J)) L_JJ^{-1}
+    for (int J = NT - 1; J >= 0; --J) {
+        const d4 ljj = adj_ld(L, ldl, n, 16 * J, 16 * J, false, true, true, lr, lg);
+        const d4 winv_t = adj_transpose(adj_inv_lower(ljj, S, lane), S, lane);
+        for (int I = 0; I < NT; ++I) {
+            d4 acc = I <= J ? adj_ld(Ab, lda, n, 16 * I, 16 * J, true, I == J, false, lr, lg)
+                            : zero;
+            for (int K = J + 1; K < NT; ++K) {
+                const d4 w = adj_ld(Ab, lda, n, 16 * I, 16 * K, false, false, false, lr, lg);
+                const d4 lt = adj_ld(L, ldl, n, 16 * J, 16 * K, true, false, false, lr, lg);
+                acc = adj_xyT(acc, w, lt, -1.0);
+            }
+            adj_st(Ab, lda, n, 16 * I, 16 * J, false, adj_xyT(zero, acc, winv_t, 1.0), lr, lg);
+        }
+        adj_fence();
+    }
+
+    // Abar = (W + W^T) / 2
+    for (int J = 0; J < NT; ++J) {
+        for (int I = J; I < NT; ++I) {
+            const d4 a = adj_ld(Ab, lda, n, 16 * I, 16 * J, false, false, false, lr, lg);
+            const d4 b = adj_ld(Ab, lda, n, 16 * I, 16 * J, true, false, false, lr, lg);
+            d4 s;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                s[r] = 0.5 * (a[r] + b[r]);
+            adj_st(Ab, lda, n, 16 * I, 16 * J, false, s, lr, lg);
+            if (I != J)
+                adj_st(Ab, lda, n, 16 * I, 16 * J, true, s, lr, lg);
+        }
+    }
+}
+
+}  // namespace mb

@@ -238,3 +238,33 @@ def uneven_device(spec: dict, seed: int, device="cuda"):
         pos = spec["off_c"][fail] + f + f * spec["n"][fail]
         X[torch.as_tensor(pos, dtype=torch.int64, device=device)] = -1.0
     return X
+
+
+# ----------------------------------------------------------------------------
+# Differentiation workload: C = chol(A) B with B n x 32.
+# ----------------------------------------------------------------------------
+
+BACKWARD_BATCH = 8192
+BACKWARD_N = 64
+BACKWARD_NB = 32
+BACKWARD_MIXED_COUNT = 2048
+BACKWARD_MIXED_LO, BACKWARD_MIXED_HI = 16, 192
+FD_DIRECTIONS = 50
+FD_STEP = 1e-6
+
+
+def backward_mixed_sizes(seed: int, count: int = BACKWARD_MIXED_COUNT) -> np.ndarray:
+    """Orders n = floor(exp(U[ln 16, ln 193))) of the mixed differentiation batch."""
+    return log_uniform_sizes(rng(seed), count, BACKWARD_MIXED_LO, BACKWARD_MIXED_HI)
+
+
+def torch_symmetric(batch: int, n: int, seed: int, device="cuda"):
+    """Device tensor (batch, n, n), column-major, symmetric with entries
+    (X + X^T)/2 of X uniform [-1, 1) (finite-difference directions)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    X = torch.empty((batch, n, n), dtype=torch.float64, device=device)
+    X.uniform_(-1.0, 1.0, generator=gen)
+    X = 0.5 * (X + X.transpose(1, 2))
+    return X.contiguous().transpose(1, 2)

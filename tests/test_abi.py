@@ -194,3 +194,46 @@ def test_plan_argument_errors(L):
     assert L.lib.mb_plan_stats(None, None, 0) == -1
     assert L.lib.mb_plan_destroy(None) == 0
     assert "plan problem" in L.status_string(L.MB_ERR_INVALID_PROBLEM)
+
+
+def test_backward_argument_errors(L):
+    f = L.dpotrf_l_backward_strided_batched
+    ok = dict(n=8, L=P, ldl=8, sL=64, Lb=P, ldlb=8, sLb=64, Ab=P, ldab=8, sAb=64, batch=2)
+
+    def call(**kw):
+        a = {**ok, **kw}
+        return f(a["n"], a["L"], a["ldl"], a["sL"], a["Lb"], a["ldlb"], a["sLb"], a["Ab"],
+                 a["ldab"], a["sAb"], a["batch"])
+    assert call(n=-1) == -1 and call(ldl=7) == -3 and call(sL=-1) == -4
+    assert call(ldlb=7) == -6 and call(sLb=-1) == -7 and call(ldab=7) == -9
+    assert call(sAb=63) == -10 and call(batch=-1) == -11
+    assert call(L=None) == -2 and call(Lb=None) == -5 and call(Ab=None) == -8
+    assert call(n=305, ldl=305, ldlb=305, ldab=305, sL=305 * 305, sLb=305 * 305,
+                sAb=305 * 305) == L.MB_ERR_UNSUPPORTED
+    assert call(n=0, L=None, Lb=None, Ab=None) == 0 and call(batch=0) == 0
+    g = L.dpotrf_l_backward_batched
+    assert g(-1, P, 8, P, 8, P, 8, 1) == -1 and g(8, P, 7, P, 8, P, 8, 1) == -3
+    assert g(8, P, 8, P, 7, P, 8, 1) == -5 and g(8, P, 8, P, 8, P, 7, 1) == -7
+    assert g(8, P, 8, P, 8, P, 8, -1) == -8 and g(8, None, 8, P, 8, P, 8, 1) == -2
+    d = L.dgemm_backward_strided_batched
+    base = ["N", "N", 4, 5, 6, 1.0, P, 4, 24, P, 6, 30, P, 4, 20, P, 4, 24, P, 6, 30, 2]
+
+    def dcall(i, v):
+        a = list(base)
+        a[i] = v
+        return d(*a)
+    assert dcall(0, "x") == -1 and dcall(1, "x") == -2 and dcall(2, -1) == -3
+    assert dcall(3, -1) == -4 and dcall(4, -1) == -5 and dcall(7, 3) == -8
+    assert dcall(8, -1) == -9 and dcall(10, 5) == -11 and dcall(11, -1) == -12
+    assert dcall(13, 3) == -14 and dcall(14, -1) == -15 and dcall(16, 3) == -17
+    assert dcall(17, 23) == -18 and dcall(19, 5) == -20 and dcall(20, 29) == -21
+    assert dcall(21, -1) == -22 and dcall(12, None) == -13 and dcall(9, None) == -10
+    assert dcall(21, 0) == 0
+    s = L.dlaset_strided_batched
+    assert s("x", 4, 4, 0.0, 0.0, P, 4, 16, 1) == -1 and s("U", -1, 4, 0.0, 0.0, P, 4, 16, 1) == -2
+    assert s("U", 4, -1, 0.0, 0.0, P, 4, 16, 1) == -3 and s("U", 4, 4, 0.0, 0.0, P, 3, 16, 1) == -7
+    assert s("U", 4, 4, 0.0, 0.0, P, 4, 15, 2) == -8 and s("U", 4, 4, 0.0, 0.0, P, 4, 16, -1) == -9
+    assert s("U", 4, 4, 0.0, 0.0, None, 4, 16, 1) == -6 and s("L", 0, 4, 0.0, 0.0, None, 1, 0, 1) == 0
+    t = L.dlaset_batched
+    assert t("q", 4, 4, 0.0, 0.0, P, 4, 1) == -1 and t("A", 4, 4, 0.0, 0.0, None, 4, 1) == -6
+    assert t("A", 4, 4, 0.0, 0.0, P, 4, -1) == -8
