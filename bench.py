@@ -282,6 +282,145 @@ def crossover(torch, _lib, inputs, args):
     print(json.dumps({"crossover": rows}))
 
 
+def time_events(torch, fn, reps, setup=None):
+    """Best and median of `reps` timed calls of fn (events on the current
+    stream); setup() runs untimed before each call."""
+    ts = []
+    for _ in range(reps):
+        if setup is not None:
+            setup()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return min(ts), float(np.median(ts))
+
+
+def uneven_batch(torch, _lib, inputs, reps):
+    """The uneven batch (100,000 problems, sizes log-uniform 4..160, 70% dgemm
+    / 30% dpotrf) through one plan: the fused persistent kernel (graph and
+    direct launch) against per-shape grouped batched calls (raw and
+    graph-captured).  Inputs are restored (untimed) before every execution,
+    since dpotrf works in place."""
+    from paper_1902_08115_amd import blas
+    spec = inputs.uneven_spec(inputs.UNEVEN_COUNT, inputs.seed_for(3, 0))
+    X0 = inputs.uneven_device(spec, inputs.seed_for(3, 200))
+    X = X0.clone()
+    info = torch.zeros(spec["count"], dtype=torch.int32, device="cuda")
+    base, ib = X.data_ptr(), info.data_ptr()
+    probs = []
+    for i in range(spec["count"]):
+        if spec["op"][i] == 0:
+            probs.append(dict(op=0, transa="NT"[spec["ta"][i]], transb="NT"[spec["tb"][i]],
+                              m=spec["m"][i], n=spec["n"][i], k=spec["k"][i], lda=spec["lda"][i],
+                              ldb=spec["ldb"][i], ldc=spec["ldc"][i], alpha=1.0, beta=1.0,
+                              A=base + 8 * int(spec["off_a"][i]),
+                              B=base + 8 * int(spec["off_b"][i]),
+                              C=base + 8 * int(spec["off_c"][i])))
+        else:
+            probs.append(dict(op=1, uplo="L", n=spec["n"][i], ldc=spec["ldc"][i],
+                              C=base + 8 * int(spec["off_c"][i]), info=ib + 4 * i))
+    t0 = time.perf_counter()
+    plan = blas.Plan(probs)
+    create_s = time.perf_counter() - t0
+    st = plan.stats()
+    g = spec["op"] == 0
+    m, n, k = spec["m"], spec["n"], spec["k"]
+    flops = float((2.0 * m * n * k)[g].sum() + (n[~g].astype(float) ** 3 / 3).sum())
+    nbytes = float(((m * k + k * n + 2 * m * n) * 8)[g].sum()
+                   + (n[~g] * (n[~g] + 1) * 8).astype(float).sum())
+    restore = lambda: X.copy_(X0)  # noqa: E731
+    res = {}
+    for mode, r in (("fused_graph", reps), ("fused", reps), ("grouped_graph", 2), ("grouped", 2)):
+        md = getattr(blas.Plan, mode.upper())
+        restore()
+        plan.execute(md)  # warm (captures the grouped graph on first use)
+        torch.cuda.synchronize()
+        best, med = time_events(torch, lambda: plan.execute(md), r, restore)
+        res[mode] = {"best_ms": round(best, 4), "median_ms": round(med, 4),
+                     "gflops": round(flops / best / 1e6, 1)}
+        log(f"uneven batch {mode}: {best:.3f} ms ({flops / best / 1e6:.0f} GFLOP/s)")
+    plan.close()
+    fb = res["fused_graph"]["best_ms"]
+    return {
+        "workload": "uneven batch: %d problems, sizes floor(exp(U[ln 4, ln 161))), 70%% dgemm "
+                    "(m, n, k independent, transa/transb uniform, alpha = beta = 1) / 30%% "
+                    "dpotrf L (SPD), tight ld, one arena" % spec["count"],
+        "flops": flops, "algorithmic_bytes": nbytes,
+        "fused_gbps": round(nbytes / fb / 1e6, 1),
+        "hbm_roofline_ms": round(nbytes / (PEAK_HBM_GBS * 1e9) * 1e3, 4),
+        "modes": res,
+        "speedup_vs_grouped": round(res["grouped"]["best_ms"] / fb, 1),
+        "speedup_vs_grouped_graph": round(res["grouped_graph"]["best_ms"] / fb, 1),
+        "plan": {k2: int(v) for k2, v in st.items()}, "plan_create_s": round(create_s, 3),
+    }
+
+
+def backward_workload(torch, _lib, inputs, reps):
+    """The differentiation workload: C = chol(A) B (B n x 32) forward and
+    backward through the autograd Functions for 8192 instances of order 64,
+    and through fused plans for 2048 instances of orders 16..192."""
+    from paper_1902_08115_amd import autograd as ag
+    from paper_1902_08115_amd.mixed import MixedCholeskyProduct
+    out = {}
+    batch, n, nb = inputs.BACKWARD_BATCH, inputs.BACKWARD_N, inputs.BACKWARD_NB
+    A = inputs.torch_spd(batch, n, seed=inputs.seed_for(4, 1))
+    B = inputs.torch_colmajor(batch, n, nb, seed=inputs.seed_for(4, 2))
+    W = inputs.torch_colmajor(batch, n, nb, seed=inputs.seed_for(4, 3))
+    Ar, Br = A.detach().requires_grad_(True), B.detach().requires_grad_(True)
+    state = {}
+
+    def fwd():
+        state["C"] = ag.cholesky_product(Ar, Br)
+
+    def bwd():
+        state["C"].backward(W)
+
+    def fresh():  # a new graph and no accumulated gradients before each timed backward
+        Ar.grad = None
+        Br.grad = None
+        fwd()
+
+    fwd()
+    bwd()
+    torch.cuda.synchronize()
+    f_best, _ = time_events(torch, fwd, reps)
+    b_best, _ = time_events(torch, bwd, reps, fresh)
+    ffl = batch * (n ** 3 / 3 + 2.0 * n * n * nb)
+    bfl = batch * (4.0 * n * n * nb + 5.0 * n ** 3 / 3)
+    out["n64_batch8192"] = {"forward_ms": round(f_best, 4), "backward_ms": round(b_best, 4),
+                            "forward_gflops": round(ffl / f_best / 1e6, 1),
+                            "backward_gflops": round(bfl / b_best / 1e6, 1)}
+    log(f"backward n=64 x 8192: forward {f_best:.3f} ms, backward {b_best:.3f} ms")
+    ns = inputs.backward_mixed_sizes(inputs.seed_for(4, 10))
+    mp = MixedCholeskyProduct(ns, nb)
+    for v in np.unique(ns):
+        idx = np.nonzero(ns == v)[0]
+        S = inputs.torch_spd(len(idx), int(v), seed=inputs.seed_for(4, 20000 + int(v)))
+        for j, b in enumerate(idx):
+            mp.view("A", int(b)).copy_(S[j])
+    gen = torch.Generator(device="cuda")
+    mp.buf["B"].uniform_(-1.0, 1.0, generator=gen.manual_seed(12))
+    mp.buf["Cbar"].uniform_(-1.0, 1.0, generator=gen.manual_seed(13))
+    mp.forward()
+    mp.backward()
+    torch.cuda.synchronize()
+    f_best, _ = time_events(torch, mp.forward, reps)
+    b_best, _ = time_events(torch, mp.backward, reps)
+    nf = ns.astype(float)
+    ffl = float((nf ** 3 / 3 + 2.0 * nf * nf * nb).sum())
+    bfl = float((4.0 * nf * nf * nb + 5.0 * nf ** 3 / 3).sum())
+    out["mixed_2048_n16_192"] = {"forward_ms": round(f_best, 4), "backward_ms": round(b_best, 4),
+                                 "forward_gflops": round(ffl / f_best / 1e6, 1),
+                                 "backward_gflops": round(bfl / b_best / 1e6, 1)}
+    log(f"backward mixed 2048: forward {f_best:.3f} ms, backward {b_best:.3f} ms")
+    mp.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,10 +431,12 @@ def main():
     ap.add_argument("--gemm-sizes", type=str, default=None)
     ap.add_argument("--potrf-sizes", type=str, default=None)
     ap.add_argument("--potrf-batch", type=int, default=None)
-    ap.add_argument("--cpu-flops-per-case", type=float, default=1.5e9)
+    ap.add_argument("--cpu-flops-per-case", type=float, default=2.0e10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--crossover", action="store_true")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the uneven-batch and differentiation measurements")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -425,6 +566,13 @@ def main():
         log("parity spot check")
         parity = parity_spot_check(torch, _lib, oracle, gemm, potrf, stream)
 
+    nxt = None
+    if not args.no_next:
+        log("uneven batch (fused plan vs grouped launches)")
+        nxt = {"uneven_batch": uneven_batch(torch, _lib, inputs, 5)}
+        log("differentiation workload")
+        nxt["backward"] = backward_workload(torch, _lib, inputs, 5)
+
     value = step_flops / (ms_per_step * 1e-3) / 1e9
     out = {
         "metric": METRIC,
@@ -455,6 +603,7 @@ def main():
         "kernels": kernels,
         "per_size": per_size,
         "parity": parity,
+        "next": nxt,
     }
     print(json.dumps(out), flush=True)
 
