@@ -95,8 +95,9 @@ def traffic_for(kernel, per_launch_bytes):
     if not ent:
         return None
     csrc = os.path.join(ROOT, "paper_1902_08115_amd", "csrc")
-    srcs = [os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".h"))]
-    if ent.get("source_digest") != source_digest(srcs):
+    names = ent.get("sources") or [f for f in os.listdir(csrc) if f.endswith((".hip", ".h"))]
+    srcs = [os.path.join(csrc, f) for f in names]
+    if not all(os.path.exists(p) for p in srcs) or ent.get("source_digest") != source_digest(srcs):
         return None
     return ent.get("bytes_per_launch")
 
@@ -299,7 +300,8 @@ def time_events(torch, fn, reps, setup=None):
     return min(ts), float(np.median(ts))
 
 
-def uneven_batch(torch, _lib, inputs, reps):
+def uneven_batch(torch, _lib, inputs, reps, modes=("fused_graph", "fused", "grouped_graph",
+                                                   "grouped")):
     """The uneven batch (100,000 problems, sizes log-uniform 4..160, 70% dgemm
     / 30% dpotrf) through one plan: the fused persistent kernel (graph and
     direct launch) against per-shape grouped batched calls (raw and
@@ -334,7 +336,8 @@ def uneven_batch(torch, _lib, inputs, reps):
                    + (n[~g] * (n[~g] + 1) * 8).astype(float).sum())
     restore = lambda: X.copy_(X0)  # noqa: E731
     res = {}
-    for mode, r in (("fused_graph", reps), ("fused", reps), ("grouped_graph", 2), ("grouped", 2)):
+    for mode in modes:
+        r = reps if mode.startswith("fused") else 2
         md = getattr(blas.Plan, mode.upper())
         restore()
         plan.execute(md)  # warm (captures the grouped graph on first use)
@@ -345,16 +348,18 @@ def uneven_batch(torch, _lib, inputs, reps):
         log(f"uneven batch {mode}: {best:.3f} ms ({flops / best / 1e6:.0f} GFLOP/s)")
     plan.close()
     fb = res["fused_graph"]["best_ms"]
+    grouped = {k: round(res[k]["best_ms"] / fb, 1) for k in ("grouped", "grouped_graph")
+               if k in res}
     return {
         "workload": "uneven batch: %d problems, sizes floor(exp(U[ln 4, ln 161))), 70%% dgemm "
                     "(m, n, k independent, transa/transb uniform, alpha = beta = 1) / 30%% "
                     "dpotrf L (SPD), tight ld, one arena" % spec["count"],
         "flops": flops, "algorithmic_bytes": nbytes,
         "fused_gbps": round(nbytes / fb / 1e6, 1),
+        "fused_traffic_bytes": traffic_for("fused_kernel", nbytes),
         "hbm_roofline_ms": round(nbytes / (PEAK_HBM_GBS * 1e9) * 1e3, 4),
         "modes": res,
-        "speedup_vs_grouped": round(res["grouped"]["best_ms"] / fb, 1),
-        "speedup_vs_grouped_graph": round(res["grouped_graph"]["best_ms"] / fb, 1),
+        "speedup_vs": grouped,
         "plan": {k2: int(v) for k2, v in st.items()}, "plan_create_s": round(create_s, 3),
     }
 
@@ -437,6 +442,10 @@ def main():
     ap.add_argument("--crossover", action="store_true")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the uneven-batch and differentiation measurements")
+    ap.add_argument("--next-only", action="store_true",
+                    help="only the uneven-batch and differentiation measurements (profiling)")
+    ap.add_argument("--uneven-modes", type=str, default="fused_graph,fused,grouped_graph,grouped",
+                    help="plan execution modes timed on the uneven batch")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -451,16 +460,26 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
 
-    args.gemm_sizes = ([int(x) for x in args.gemm_sizes.split(",")] if args.gemm_sizes
-                       else list(inputs.GEMM_SWEEP_SIZES))
-    args.potrf_sizes = ([int(x) for x in args.potrf_sizes.split(",")] if args.potrf_sizes
-                        else list(inputs.POTRF_SWEEP_SIZES))
+    def sizes(text, default):
+        if not text:
+            return list(default)
+        if text == "none":
+            return []
+        return [int(x) for x in text.split(",")]
+    args.gemm_sizes = sizes(args.gemm_sizes, inputs.GEMM_SWEEP_SIZES)
+    args.potrf_sizes = sizes(args.potrf_sizes, inputs.POTRF_SWEEP_SIZES)
     args.potrf_batch = args.potrf_batch or inputs.POTRF_SWEEP_BATCH
     if args.copies is None:
         args.copies = max(1, min(12, args.warmup + args.steps))
 
     if args.crossover:
         crossover(torch, _lib, inputs, args)
+        return
+    if args.next_only:
+        nxt = {"uneven_batch": uneven_batch(torch, _lib, inputs, args.steps,
+                                            args.uneven_modes.split(","))}
+        nxt["backward"] = backward_workload(torch, _lib, inputs, args.steps)
+        print(json.dumps({"next": nxt}), flush=True)
         return
 
     log(f"device {torch.cuda.get_device_name(0)}; generating inputs")
@@ -569,7 +588,7 @@ def main():
     nxt = None
     if not args.no_next:
         log("uneven batch (fused plan vs grouped launches)")
-        nxt = {"uneven_batch": uneven_batch(torch, _lib, inputs, 5)}
+        nxt = {"uneven_batch": uneven_batch(torch, _lib, inputs, 5, args.uneven_modes.split(","))}
         log("differentiation workload")
         nxt["backward"] = backward_workload(torch, _lib, inputs, 5)
 
