@@ -312,6 +312,27 @@ typedef struct mb_plan mb_plan;
 int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
                    int64_t *bad_index);
 
+/*
+ * Tuning overrides for mb_plan_create_ex (the autotuner's measurement
+ * hooks; results never depend on them).  A negative field keeps the tuned
+ * default.
+ *   tile_two_min  a side of a dgemm register tile uses two 16-wide MFMA
+ *                 blocks when that dimension of C exceeds this value.
+ *   potrf_waves   waves of each 4-wave workgroup that start on the dpotrf /
+ *                 Cholesky-adjoint class (0..4); the default follows that
+ *                 class's share of the estimated work.
+ */
+typedef struct mb_plan_options {
+    int tile_two_min;
+    int potrf_waves;
+} mb_plan_options;
+
+/* mb_plan_create with tuning overrides (options may be NULL).  Positions:
+ * problems 1, count 2, options 3 (-3: potrf_waves above 4), plan 4,
+ * bad_index 5; mb_plan_create reports a NULL plan as -3. */
+int mb_plan_create_ex(const mb_problem *problems, int64_t count, const mb_plan_options *options,
+                      mb_plan **plan, int64_t *bad_index);
+
 /* Execution modes of mb_plan_execute_mode. */
 #define MB_PLAN_FUSED_GRAPH 0   /* the captured persistent launch (mb_plan_execute) */
 #define MB_PLAN_FUSED 1         /* the same two kernels launched directly          */

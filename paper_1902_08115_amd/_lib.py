@@ -31,10 +31,15 @@ EXPORTS = (
     "mb_dpotrf_kernel_name",
     "mb_dgemm_backward_strided_batched", "mb_dpotrf_l_backward_strided_batched",
     "mb_dpotrf_l_backward_batched", "mb_dlaset_strided_batched", "mb_dlaset_batched",
-    "mb_plan_create", "mb_plan_execute", "mb_plan_execute_mode", "mb_plan_stats",
+    "mb_plan_create", "mb_plan_create_ex", "mb_plan_execute", "mb_plan_execute_mode", "mb_plan_stats",
     "mb_plan_destroy",
     "mb_status_string", "mb_version",
 )
+
+
+class PlanOptions(ctypes.Structure):
+    """struct mb_plan_options (negative fields keep the tuned defaults)."""
+    _fields_ = [("tile_two_min", ctypes.c_int), ("potrf_waves", ctypes.c_int)]
 
 
 class Problem(ctypes.Structure):
@@ -105,6 +110,7 @@ def _load():
     lib.mb_dlaset_batched.argtypes = [c_char, c_int, c_int, c_double, c_double, vp, c_int, c_int,
                                       vp]
     lib.mb_plan_create.argtypes = [vp, c_i64, ctypes.POINTER(vp), ctypes.POINTER(c_i64)]
+    lib.mb_plan_create_ex.argtypes = [vp, c_i64, vp, ctypes.POINTER(vp), ctypes.POINTER(c_i64)]
     lib.mb_plan_execute.argtypes = [vp, vp]
     lib.mb_plan_execute_mode.argtypes = [vp, c_int, vp]
     lib.mb_plan_stats.argtypes = [vp, ctypes.POINTER(c_i64), c_int]
@@ -247,13 +253,20 @@ def problems_array(problems):
     return arr
 
 
-def plan_create(problems):
-    """(status, handle or None, bad_index) for a ctypes Problem array."""
+def plan_create(problems, tile_two_min=None, potrf_waves=None):
+    """(status, handle or None, bad_index) for a ctypes Problem array; the
+    keyword arguments are the tuning overrides of mb_plan_create_ex."""
     h = ctypes.c_void_p()
     bad = ctypes.c_int64(-1)
     n = len(problems)
-    st = lib.mb_plan_create(ctypes.cast(problems, ctypes.c_void_p) if n else None, n,
-                            ctypes.byref(h), ctypes.byref(bad))
+    arr = ctypes.cast(problems, ctypes.c_void_p) if n else None
+    if tile_two_min is None and potrf_waves is None:
+        st = lib.mb_plan_create(arr, n, ctypes.byref(h), ctypes.byref(bad))
+    else:
+        opt = PlanOptions(-1 if tile_two_min is None else int(tile_two_min),
+                          -1 if potrf_waves is None else int(potrf_waves))
+        st = lib.mb_plan_create_ex(arr, n, ctypes.cast(ctypes.pointer(opt), ctypes.c_void_p),
+                                   ctypes.byref(h), ctypes.byref(bad))
     return st, (h.value if st == MB_OK else None), bad.value
 
 

@@ -14,6 +14,13 @@ by measurement and differs per routine and architecture) applied to the
 kernel menu of this library.  Needs a GPU:
 
   python -m paper_1902_08115_amd.autotune --out-dir gpurun_out
+
+With --fused it tunes the fused uneven batch instead and writes
+fused_tuned.h: the wave time of every task kind is measured on homogeneous
+plans (time x resident waves / tasks, i.e. under full load) and fitted to the
+cost model the plan orders and balances work by, and the register-tile
+threshold is chosen by timing the 100,000-problem uneven batch with each
+candidate.
 """
 from __future__ import annotations
 
@@ -73,12 +80,197 @@ constexpr int kGemmTune[4][kGemmTuneEntries][2] = {{
 """
 
 
+def fused_header(c):
+    p = ", ".join("%.1f" % x for x in c["potrf"])
+    a = ", ".join("%.1f" % x for x in c["adjoint"])
+    return f"""// fused_tuned.h -- cost model and tile rule of the fused uneven batch.
+//
+// Written by paper_1902_08115_amd/autotune.py (--fused) from measurements on
+// MI355X: homogeneous batches of each task kind are timed through the fused
+// kernel, and the wave time of one task (time x resident waves / tasks) is
+// fitted as
+//   dgemm tile   F + T * TM * TN + chunks * (M * TM * TN + L * (TM + TN))
+//   dpotrf       P0 + P1 * nt + P2 * nt^2 + P3 * nt^3
+//   adjoint      the same cubic with its own coefficients
+// with chunks = ceil(k / 16) and nt = ceil(n / 16); a side of the register
+// tile uses two 16-row MFMA blocks when that dimension exceeds kFusedTwoMin
+// (chosen by timing the uneven batch).  Estimates order the work (longest
+// first) and balance the per-XCD queues; they never change results.
+#pragma once
+
+namespace mb {{
+
+constexpr double kFusedGemmFixedNs = {c["F"]:.1f};
+constexpr double kFusedGemmTileNs = {c["T"]:.1f};
+constexpr double kFusedGemmMfmaNs = {c["M"]:.1f};
+constexpr double kFusedGemmLoadNs = {c["L"]:.1f};
+constexpr double kFusedPotrfNs[4] = {{{p}}};
+constexpr double kFusedAdjointNs[4] = {{{a}}};
+constexpr double kFusedLasetNs = {c["laset"]:.1f};
+constexpr int kFusedTwoMin = {c["two_min"]};
+// waves of a 4-wave workgroup that start on the dpotrf class:
+// round(4 * min(1, share * kFusedPotrfShareScale)), share = that class's
+// estimated fraction of the work (measured best split on the uneven batch)
+constexpr double kFusedPotrfShareScale = {c["share_scale"]:.3f};
+
+}}  // namespace mb
+"""
+
+
+def fused_tune(args):
+    import numpy as np
+    import torch
+
+    from paper_1902_08115_amd import _lib, blas, inputs
+    waves = None
+    rows = {"gemm": [], "potrf": [], "adjoint": [], "uneven": []}
+
+    def run_plan(probs, restore=None, reps=args.reps, **opt):
+        plan = blas.Plan(probs, **opt)
+        st = plan.stats()
+        best = 1e30
+        for r in range(reps + 1):
+            if restore is not None:
+                restore()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.execute(blas.Plan.FUSED)
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                best = min(best, e0.elapsed_time(e1))
+        plan.close()
+        return best, st
+
+    # dgemm tiles: (TM, TN) from m, n around the threshold; k from 16 to 160
+    for (m, n) in ((16, 16), (32, 32), (16, 32), (32, 16)):
+        for k in (16, 32, 64, 128, 160):
+            batch = min(60000, (1 << 30) // (8 * (m * k + k * n + m * n)))
+            A = inputs.torch_colmajor(batch, m, k, seed=1)
+            B = inputs.torch_colmajor(batch, k, n, seed=2)
+            C = inputs.torch_colmajor(batch, m, n, seed=3)
+            probs = [dict(op=0, transa="N", transb="N", m=m, n=n, k=k, lda=m, ldb=k, ldc=m,
+                          alpha=1.0, beta=1.0, A=A.data_ptr() + 8 * m * k * b,
+                          B=B.data_ptr() + 8 * k * n * b, C=C.data_ptr() + 8 * m * n * b)
+                     for b in range(batch)]
+            ms, st = run_plan(probs, tile_two_min=16)
+            waves = st["workgroups"] * 4
+            wt = ms * 1e6 * waves / st["units"]
+            rows["gemm"].append((2 if m > 16 else 1, 2 if n > 16 else 1, (k + 15) // 16, wt))
+            log(f"fused gemm {m}x{n}x{k}: {ms:.3f} ms, {wt:.0f} ns per tile")
+            del A, B, C
+    # dpotrf and adjoint
+    for n in (16, 32, 48, 64, 96, 128, 160, 192, 256):
+        batch = min(16384, (1 << 30) // (8 * n * n))
+        M = inputs.torch_spd(batch, n, seed=5)
+        X = M.clone()
+        info = torch.zeros(batch, dtype=torch.int32, device="cuda")
+        probs = [dict(op=1, uplo="L", n=n, ldc=n, C=X.data_ptr() + 8 * n * n * b,
+                      info=info.data_ptr() + 4 * b) for b in range(batch)]
+        ms, st = run_plan(probs, restore=lambda: X.copy_(M), potrf_waves=4)
+        wt = ms * 1e6 * st["workgroups"] * 4 / st["units"]
+        rows["potrf"].append(((n + 15) // 16, wt))
+        log(f"fused potrf n={n}: {ms:.3f} ms, {wt:.0f} ns per task")
+        Lb = inputs.torch_colmajor(batch, n, n, seed=6)
+        Ab = torch.empty_like(Lb)
+        probs = [dict(op=2, n=n, A=M.data_ptr() + 8 * n * n * b, lda=n,
+                      B=Lb.data_ptr() + 8 * n * n * b, ldb=n, C=Ab.data_ptr() + 8 * n * n * b,
+                      ldc=n) for b in range(batch)]
+        # the adjoint of the factor of M: factor once, then time the adjoint
+        X.copy_(M)
+        assert _lib.dpotrf_strided_batched("L", n, X.data_ptr(), n, n * n, info.data_ptr(), batch,
+                                           torch.cuda.current_stream().cuda_stream) == 0
+        for p in probs:
+            p["A"] = p["A"] - M.data_ptr() + X.data_ptr()
+        ms, st = run_plan(probs, potrf_waves=4)
+        wt = ms * 1e6 * st["workgroups"] * 4 / st["units"]
+        rows["adjoint"].append(((n + 15) // 16, wt))
+        log(f"fused adjoint n={n}: {ms:.3f} ms, {wt:.0f} ns per task")
+        del M, X, Lb, Ab
+    torch.cuda.empty_cache()
+
+    # least squares on relative error (rows scaled by 1 / measured time), so
+    # that short tasks are fitted as well as long ones
+    g = np.array(rows["gemm"], dtype=float)
+    tm, tn, ch, wt = g[:, 0], g[:, 1], g[:, 2], g[:, 3]
+    X = np.stack([np.ones_like(tm), tm * tn, ch * tm * tn, ch * (tm + tn)], 1)
+    F, T, Mc, Lc = np.linalg.lstsq(X / wt[:, None], np.ones_like(wt), rcond=None)[0]
+    coef = {"F": F, "T": T, "M": Mc, "L": Lc}
+    for kind in ("potrf", "adjoint"):
+        q = np.array(rows[kind], dtype=float)
+        V = np.stack([np.ones(len(q)), q[:, 0], q[:, 0] ** 2, q[:, 0] ** 3], 1)
+        coef[kind] = list(np.linalg.lstsq(V / q[:, 1:2], np.ones(len(q)), rcond=None)[0])
+    coef["laset"] = 2000.0
+
+    # the tile threshold, timed on the uneven batch
+    spec = inputs.uneven_spec(inputs.UNEVEN_COUNT, inputs.seed_for(3, 0))
+    X0 = inputs.uneven_device(spec, inputs.seed_for(3, 200))
+    Xw = X0.clone()
+    info = torch.zeros(spec["count"], dtype=torch.int32, device="cuda")
+    base = Xw.data_ptr()
+    probs = []
+    for i in range(spec["count"]):
+        if spec["op"][i] == 0:
+            probs.append(dict(op=0, transa="NT"[spec["ta"][i]], transb="NT"[spec["tb"][i]],
+                              m=spec["m"][i], n=spec["n"][i], k=spec["k"][i], lda=spec["lda"][i],
+                              ldb=spec["ldb"][i], ldc=spec["ldc"][i], alpha=1.0, beta=1.0,
+                              A=base + 8 * int(spec["off_a"][i]), B=base + 8 * int(spec["off_b"][i]),
+                              C=base + 8 * int(spec["off_c"][i])))
+        else:
+            probs.append(dict(op=1, uplo="L", n=spec["n"][i], ldc=spec["ldc"][i],
+                              C=base + 8 * int(spec["off_c"][i]), info=info.data_ptr() + 4 * i))
+    arr = _lib.problems_array(probs)
+    best_t, best_ms = None, 1e30
+    for t in (8, 16, 24, 32, 48):
+        ms, _ = run_plan(arr, restore=lambda: Xw.copy_(X0), tile_two_min=t)
+        rows["uneven"].append((t, ms))
+        log(f"uneven batch, tile threshold {t}: {ms:.3f} ms")
+        if ms < best_ms:
+            best_t, best_ms = t, ms
+    coef["two_min"] = best_t
+    # the dpotrf class's share of the waves: the model's share of the work
+    # scaled so that the plan's rule reproduces the best measured split
+    tmv = np.where(spec["m"] > best_t, 2, 1)
+    tnv = np.where(spec["n"] > best_t, 2, 1)
+    gm = spec["op"] == 0
+    tiles = np.ceil(spec["m"] / (16 * tmv)) * np.ceil(spec["n"] / (16 * tnv))
+    chv = np.ceil(spec["k"] / 16)
+    gem = float((tiles * (F + T * tmv * tnv + chv * (Mc * tmv * tnv + Lc * (tmv + tnv))))[gm].sum())
+    ntv = np.ceil(spec["n"][~gm] / 16)
+    pc = coef["potrf"]
+    pot = float((pc[0] + pc[1] * ntv + pc[2] * ntv ** 2 + pc[3] * ntv ** 3).sum())
+    share = pot / (pot + gem)
+    best_w, best_ms = None, 1e30
+    for w in (1, 2, 3):
+        ms, _ = run_plan(arr, restore=lambda: Xw.copy_(X0), tile_two_min=best_t, potrf_waves=w)
+        rows["uneven"].append(("potrf_waves", w, ms))
+        log(f"uneven batch, dpotrf-class waves {w}: {ms:.3f} ms")
+        if ms < best_ms:
+            best_w, best_ms = w, ms
+    coef["share_scale"] = best_w / (4.0 * share)
+    log(f"model dpotrf share {share:.3f}; best waves {best_w}; scale {coef['share_scale']:.3f}")
+    os.makedirs(args.out_dir, exist_ok=True)
+    with open(os.path.join(args.out_dir, "fused_tuned.h"), "w") as f:
+        f.write(fused_header(coef))
+    with open(os.path.join(args.out_dir, "autotune_fused.json"), "w") as f:
+        json.dump({"rows": rows, "coef": {k: (list(map(float, v)) if isinstance(v, list) else
+                                              float(v)) for k, v in coef.items()},
+                   "time": time.strftime("%Y-%m-%d %H:%M:%S")}, f, indent=1)
+    log("wrote fused_tuned.h and autotune_fused.json")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out-dir", default=".")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--sizes", default=None)
+    ap.add_argument("--fused", action="store_true", help="tune the fused uneven batch")
     args = ap.parse_args()
+    if args.fused:
+        fused_tune(args)
+        return
     sizes = [int(x) for x in args.sizes.split(",")] if args.sizes else list(SIZES)
 
     import torch

@@ -149,9 +149,9 @@ class Plan:
     FUSED_GRAPH, FUSED, GROUPED, GROUPED_GRAPH = (_lib.PLAN_FUSED_GRAPH, _lib.PLAN_FUSED,
                                                   _lib.PLAN_GROUPED, _lib.PLAN_GROUPED_GRAPH)
 
-    def __init__(self, problems):
+    def __init__(self, problems, tile_two_min=None, potrf_waves=None):
         arr = problems if isinstance(problems, ctypes.Array) else _lib.problems_array(problems)
-        st, self._h, bad = _lib.plan_create(arr)
+        st, self._h, bad = _lib.plan_create(arr, tile_two_min, potrf_waves)
         if st != _lib.MB_OK:
             raise MbError(f"mb_plan_create (problem {bad})", st)
 

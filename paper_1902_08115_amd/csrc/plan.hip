@@ -292,6 +292,18 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
     if (count > 0 && !problems) return -1;
     if (count < 0) return -2;
     if (!plan) return -3;
+    return mb_plan_create_ex(problems, count, nullptr, plan, bad_index);
+}
+
+int mb_plan_create_ex(const mb_problem *problems, int64_t count, const mb_plan_options *options,
+                      mb_plan **plan, int64_t *bad_index)
+{
+    if (count > 0 && !problems) return -1;
+    if (count < 0) return -2;
+    if (!plan) return -4;
+    if (options && options->potrf_waves > mb::kFusedWaves) return -3;
+    const int two_min =
+        (options && options->tile_two_min >= 0) ? options->tile_two_min : mb::kFusedTwoMin;
     *plan = nullptr;
     if (count > (int64_t)UINT32_MAX) return MB_ERR_UNSUPPORTED;
 
@@ -321,8 +333,8 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
         if (q.op == MB_OP_DGEMM) {
             const int ta = tcode(q.transa), tb = tcode(q.transb);
             const bool scale_only = q.alpha == 0.0 || q.k == 0;
-            const int tm = q.m > mb::kFusedTwoMin ? 2 : 1;
-            const int tn = q.n > mb::kFusedTwoMin ? 2 : 1;
+            const int tm = q.m > two_min ? 2 : 1;
+            const int tn = q.n > two_min ? 2 : 1;
             d.A = scale_only ? nullptr : q.A;
             d.B = scale_only ? nullptr : q.B;
             d.C = q.C;
@@ -403,14 +415,18 @@ int mb_plan_create(const mb_problem *problems, int64_t count, mb_plan **plan,
     for (int64_t i = 0; i < nd; ++i)
         if (!long_kind(i)) gemm_ns += unit_ns[i] * nunits[i];
     // waves of a workgroup that start on the dpotrf class: in proportion to
-    // its share of the estimated work, at least one while both classes exist
+    // its share of the estimated work (scaled by the measured best split), at
+    // least one while both classes exist
     int potrf_waves = 0;
-    {
+    if (options && options->potrf_waves >= 0) {
+        potrf_waves = options->potrf_waves;
+    } else {
         const double potrf_ns = total_ns - gemm_ns;
         if (potrf_ns > 0.0 && gemm_ns <= 0.0) {
             potrf_waves = mb::kFusedWaves;
         } else if (potrf_ns > 0.0) {
-            potrf_waves = (int)(mb::kFusedWaves * potrf_ns / total_ns + 0.5);
+            const double share = std::min(1.0, potrf_ns / total_ns * mb::kFusedPotrfShareScale);
+            potrf_waves = (int)(mb::kFusedWaves * share + 0.5);
             potrf_waves = std::min(std::max(potrf_waves, 1), mb::kFusedWaves - 1);
         }
     }

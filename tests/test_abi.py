@@ -237,3 +237,17 @@ def test_backward_argument_errors(L):
     t = L.dlaset_batched
     assert t("q", 4, 4, 0.0, 0.0, P, 4, 1) == -1 and t("A", 4, 4, 0.0, 0.0, None, 4, 1) == -6
     assert t("A", 4, 4, 0.0, 0.0, P, 4, -1) == -8
+
+
+def test_plan_options_errors(L):
+    import ctypes
+    h = ctypes.c_void_p()
+    bad = ctypes.c_int64(-1)
+    arr = L.problems_array([dict(op=7)])
+    opt = L.PlanOptions(16, 5)
+    vp = lambda x: ctypes.cast(x, ctypes.c_void_p)  # noqa: E731
+    assert L.lib.mb_plan_create_ex(vp(arr), 1, vp(ctypes.pointer(opt)), ctypes.byref(h),
+                                   ctypes.byref(bad)) == -3
+    assert L.lib.mb_plan_create_ex(vp(arr), 1, None, None, None) == -4
+    st, hd, idx = L.plan_create(arr, tile_two_min=32, potrf_waves=2)
+    assert (st, hd, idx) == (L.MB_ERR_INVALID_PROBLEM, None, 0)
