@@ -364,6 +364,43 @@ def uneven_batch(torch, _lib, inputs, reps, modes=("fused_graph", "fused", "grou
     }
 
 
+def skinny_sweeps(torch, _lib, inputs, reps):
+    """The paper's rectangular sweeps (App. C): m = n = 4 with k = s, m = 4
+    with n = k = s, n = 4 with m = k = s, s over the square sweep sizes, every
+    trans case, through the shape-aware dispatch; batch for ~1 GiB of
+    operands per point (beyond the 256 MiB last-level cache).  Reports the
+    kernel chosen and GFLOP/s and GB/s."""
+    sh = torch.cuda.current_stream().cuda_stream
+    out = []
+    for label, shape in (("m=n=4", lambda s: (4, 4, s)), ("m=4", lambda s: (4, s, s)),
+                         ("n=4", lambda s: (s, 4, s))):
+        for s in inputs.GEMM_SWEEP_SIZES:
+            m, n, k = shape(s)
+            for t in inputs.TRANS_CASES:
+                ar, ac = (m, k) if t[0] == "N" else (k, m)
+                br, bc = (k, n) if t[1] == "N" else (n, k)
+                batch = min(1 << 22, (1 << 30) // (8 * (m * k + k * n + m * n)))
+                A = inputs.torch_colmajor(batch, ar, ac, seed=21)
+                B = inputs.torch_colmajor(batch, br, bc, seed=22)
+                C = inputs.torch_colmajor(batch, m, n, seed=23)
+                fn = lambda: _lib.dgemm_strided_batched(  # noqa: E731
+                    t[0], t[1], m, n, k, 1.0, A.data_ptr(), ar, ar * ac, B.data_ptr(), br,
+                    br * bc, 1.0, C.data_ptr(), m, m * n, batch, sh)
+                fn()
+                best, _ = time_events(torch, fn, reps)
+                fl = 2.0 * m * n * k * batch
+                by = 8.0 * (m * k + k * n + 2 * m * n) * batch
+                out.append({"sweep": label, "m": m, "n": n, "k": k, "trans": t, "batch": batch,
+                            "kernel": _lib.dgemm_kernel_name(t[0], t[1], m, n, k),
+                            "ms": round(best, 4), "gflops": round(fl / best / 1e6, 1),
+                            "gbps": round(by / best / 1e6, 1)})
+                del A, B, C
+            log(f"skinny {label} s={s}: " + " ".join(
+                f"{r['trans']} {r['gbps']:.0f}GB/s" for r in out[-4:]))
+    torch.cuda.empty_cache()
+    return out
+
+
 def backward_workload(torch, _lib, inputs, reps):
     """The differentiation workload: C = chol(A) B (B n x 32) forward and
     backward through the autograd Functions for 8192 instances of order 64,
@@ -444,6 +481,8 @@ def main():
                     help="skip the uneven-batch and differentiation measurements")
     ap.add_argument("--next-only", action="store_true",
                     help="only the uneven-batch and differentiation measurements (profiling)")
+    ap.add_argument("--skinny", action="store_true",
+                    help="also measure the thin / flat / small dgemm sweeps")
     ap.add_argument("--uneven-modes", type=str, default="fused_graph,fused,grouped_graph,grouped",
                     help="plan execution modes timed on the uneven batch")
     args = ap.parse_args()
@@ -479,6 +518,8 @@ def main():
         nxt = {"uneven_batch": uneven_batch(torch, _lib, inputs, args.steps,
                                             args.uneven_modes.split(","))}
         nxt["backward"] = backward_workload(torch, _lib, inputs, args.steps)
+        if args.skinny:
+            nxt["skinny"] = skinny_sweeps(torch, _lib, inputs, args.steps)
         print(json.dumps({"next": nxt}), flush=True)
         return
 
@@ -591,6 +632,9 @@ def main():
         nxt = {"uneven_batch": uneven_batch(torch, _lib, inputs, 5, args.uneven_modes.split(","))}
         log("differentiation workload")
         nxt["backward"] = backward_workload(torch, _lib, inputs, 5)
+        if args.skinny:
+            log("thin / flat / small dgemm sweeps")
+            nxt["skinny"] = skinny_sweeps(torch, _lib, inputs, 5)
 
     value = step_flops / (ms_per_step * 1e-3) / 1e9
     out = {

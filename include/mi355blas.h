@@ -61,6 +61,9 @@ extern "C" {
 #define MB_VARIANT_DIRECT 1 /* operands read straight into registers, no LDS   */
 #define MB_VARIANT_PACKED 2 /* operand panels staged (and transposed) in LDS,  */
                             /* FP64 MFMA rank-4 updates                        */
+#define MB_VARIANT_REGTILE 3 /* register tiles of 16-wide MFMA blocks read    */
+                             /* straight from global memory (thin, flat and   */
+                             /* small results)                                */
 
 /* ---------------------------------------------------------------- dgemm --- */
 
@@ -141,7 +144,7 @@ const char *mb_dgemm_config_name(int config);
  * an out-of-range configuration. */
 int mb_dgemm_config_max_mn(int config);
 
-/* Host-only query: the kernel family (MB_VARIANT_DIRECT or MB_VARIANT_PACKED)
+/* Host-only query: the kernel family (MB_VARIANT_DIRECT, _PACKED or _REGTILE)
  * that the plain calls select for this shape, or -1 for an illegal trans. */
 int mb_dgemm_select(char transa, char transb, int m, int n, int k);
 

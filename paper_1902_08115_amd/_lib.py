@@ -16,7 +16,7 @@ MB_OK = 0
 MB_ERR_HIP = -1000
 MB_ERR_UNSUPPORTED = -1001
 MB_ERR_INVALID_PROBLEM = -1002
-VARIANT_AUTO, VARIANT_DIRECT, VARIANT_PACKED = 0, 1, 2
+VARIANT_AUTO, VARIANT_DIRECT, VARIANT_PACKED, VARIANT_REGTILE = 0, 1, 2, 3
 OP_DGEMM, OP_DPOTRF, OP_DPOTRF_ADJOINT, OP_DLASET = 0, 1, 2, 3
 PLAN_FUSED_GRAPH, PLAN_FUSED, PLAN_GROUPED, PLAN_GROUPED_GRAPH = 0, 1, 2, 3
 PLAN_STATS = ("problems", "units", "gemm_groups", "other_groups", "workgroups", "waves_per_cu",

@@ -52,19 +52,29 @@ def time_call(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def header(table):
-    rows = []
-    for t in TRANS:
-        ent = ", ".join("{%d, %d}" % (v, c) for v, c in table[t])
-        rows.append("    {" + ent + "},")
+def header(table, skinny):
+    def block(tab, indent):
+        rows = []
+        for t in TRANS:
+            ent = ", ".join("{%d, %d}" % (v, c) for v, c in tab[t])
+            rows.append(indent + "{" + ent + "},")
+        return chr(10).join(rows)
     dims = ", ".join(str(x) if x < (1 << 30) else "1 << 30" for x in CLASS_MAX)
-    return f"""// gemm_tuned.h -- size-class dispatch table of the batched dgemm.
+    sk = chr(10).join("    {" + chr(10) + block(skinny[c], "        ") + chr(10) + "    },"
+                      for c in range(3))
+    return f"""// gemm_tuned.h -- size-class dispatch tables of the batched dgemm.
 //
 // Written by paper_1902_08115_amd/autotune.py from measurements on MI355X
-// (square batched sweep, every trans case); edit by re-running the tuner.
-// Entry e of the table for trans case (2*ta + tb) applies while
-// max(m, n, k) <= kGemmTuneMaxDim[e]; variant 1 = direct kernel, 2 = packed
-// kernel with the given configuration of the packed menu.
+// (square sweep and the thin / flat / small sweeps of every trans case); edit
+// by re-running the tuner.
+// Square table (m > 16 and n > 16): entry e for trans case (2*ta + tb)
+// applies while max(m, n, k) <= kGemmTuneMaxDim[e].  Skinny tables
+// kGemmSkinny[s]: s = 0 for m <= 16 and n <= 16 (class of k; the square
+// sizes up to 16 fall here), s = 1 for m <= 16 < n (class of max(n, k)),
+// s = 2 for n <= 16 < m (class of max(m, k)).  Variant 1 = direct kernel,
+// 2 = packed kernel with the given configuration of the packed menu,
+// 3 = register tiles (one 16-wide MFMA block per side of 16 or less, two
+// otherwise).
 #pragma once
 
 namespace mb {{
@@ -73,7 +83,12 @@ constexpr int kGemmTuneEntries = {len(CLASS_MAX)};
 constexpr int kGemmTuneMaxDim[kGemmTuneEntries] = {{{dims}}};
 // {{variant, packed configuration}} per trans case and size class
 constexpr int kGemmTune[4][kGemmTuneEntries][2] = {{
-{chr(10).join(rows)}
+{block(table, "    ")}
+}};
+
+// {{variant, packed configuration}} per skinny class, trans case and size class
+constexpr int kGemmSkinny[3][4][kGemmTuneEntries][2] = {{
+{sk}
 }};
 
 }}  // namespace mb
@@ -267,6 +282,7 @@ def main():
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--sizes", default=None)
     ap.add_argument("--fused", action="store_true", help="tune the fused uneven batch")
+    ap.add_argument("--square-only", action="store_true", help="skip the thin / flat sweeps")
     args = ap.parse_args()
     if args.fused:
         fused_tune(args)
@@ -281,55 +297,86 @@ def main():
     names = [_lib.dgemm_config_name(c) for c in range(ncfg)]
     limit = [_lib.dgemm_config_max_mn(c) for c in range(ncfg)]
     results = []
-    best = {t: {} for t in TRANS}
-    for n in sizes:
-        batch = inputs.gemm_sweep_batch(n)
-        A = inputs.torch_colmajor(batch, n, n, seed=11)
-        B = inputs.torch_colmajor(batch, n, n, seed=12)
-        C = inputs.torch_colmajor(batch, n, n, seed=13)
+
+    def measure(m, n, k, t, label):
+        """Time every applicable candidate on a ~1 GiB batch of (m, n, k)."""
+        ar, ac = (m, k) if t[0] == "N" else (k, m)
+        br, bc = (k, n) if t[1] == "N" else (n, k)
+        batch = min(1 << 22, (1 << 30) // (8 * (m * k + k * n + m * n)))
+        A = inputs.torch_colmajor(batch, ar, ac, seed=11)
+        B = inputs.torch_colmajor(batch, br, bc, seed=12)
+        C = inputs.torch_colmajor(batch, m, n, seed=13)
         pa, pb, pc = A.data_ptr(), B.data_ptr(), C.data_ptr()
-        for t in TRANS:
-            cands = [("direct", None)] + [(names[c], c) for c in range(ncfg) if limit[c] >= n]
-            timings = {}
-            for name, cfg in cands:
-                if cfg is None:
-                    def fn():
-                        st = _lib.dgemm_strided_batched(t[0], t[1], n, n, n, 1.0, pa, n, n * n,
-                                                        pb, n, n * n, 1.0, pc, n, n * n, batch,
-                                                        sh, _lib.VARIANT_DIRECT)
-                        assert st == 0, st
-                else:
-                    def fn(cfg=cfg):
-                        st = _lib.dgemm_strided_batched_config(t[0], t[1], n, n, n, 1.0, pa, n,
-                                                               n * n, pb, n, n * n, 1.0, pc, n,
-                                                               n * n, batch, cfg, sh)
-                        assert st == 0, st
-                timings[name] = time_call(torch, fn, args.reps)
-            win = min(timings, key=timings.get)
-            best[t][n] = (1, -1) if win == "direct" else (2, names.index(win))
-            flops = 2.0 * n ** 3 * batch
-            results.append({"n": n, "trans": t, "batch": batch, "ms": timings, "best": win,
-                            "best_gflops": flops / timings[win] / 1e6})
-            log(f"n={n} {t}: best {win} {flops / timings[win] / 1e6:.0f} GF/s "
-                + " ".join(f"{k.replace('gemm_packed_', '')}={v:.3f}" for k, v in timings.items()))
+        sA, sB, sC = ar * ac, br * bc, m * n
+        cands = [("direct", 1, -1), ("regtile", 3, -1)] + [
+            (names[c], 2, c) for c in range(ncfg) if limit[c] >= max(m, n)]
+        timings = {}
+        for name, var, cfg in cands:
+            if cfg < 0:
+                def fn(var=var):
+                    st = _lib.dgemm_strided_batched(t[0], t[1], m, n, k, 1.0, pa, ar, sA, pb, br,
+                                                    sB, 1.0, pc, m, sC, batch, sh, var)
+                    assert st == 0, st
+            else:
+                def fn(cfg=cfg):
+                    st = _lib.dgemm_strided_batched_config(t[0], t[1], m, n, k, 1.0, pa, ar, sA,
+                                                           pb, br, sB, 1.0, pc, m, sC, batch,
+                                                           cfg, sh)
+                    assert st == 0, st
+            timings[name] = time_call(torch, fn, args.reps)
+        win = min(timings, key=timings.get)
+        flops = 2.0 * m * n * k * batch
+        results.append({"sweep": label, "m": m, "n": n, "k": k, "trans": t, "batch": batch,
+                        "ms": timings, "best": win, "best_gflops": flops / timings[win] / 1e6})
+        log(f"{label} {m}x{n}x{k} {t}: best {win} {flops / timings[win] / 1e6:.0f} GF/s " + " ".join(
+            f"{kk.replace('gemm_packed_', '')}={v:.3f}" for kk, v in timings.items()))
         del A, B, C
         torch.cuda.empty_cache()
+        if win == "direct":
+            return (1, -1)
+        if win == "regtile":
+            return (3, -1)
+        return (2, names.index(win))
 
-    table = {}
-    for t in TRANS:
-        row = []
-        for cm in CLASS_MAX:
-            # the class is represented by the largest measured size inside it
-            inside = [n for n in best[t] if n <= cm]
-            n = max(inside) if inside else min(best[t])
-            v, c = best[t][n]
-            if cm > 320 and v == 2 and limit[c] < (1 << 30):
-                c = names.index("gemm_packed_tile64_k16")
-            row.append((v, c))
-        table[t] = row
+    def to_table(best):
+        table = {}
+        for t in TRANS:
+            row = []
+            for cm in CLASS_MAX:
+                # a class is represented by the largest measured size inside it
+                inside = [n for n in best[t] if n <= cm]
+                n = max(inside) if inside else min(best[t])
+                v, c = best[t][n]
+                if cm > 320 and v == 2 and limit[c] < (1 << 30):
+                    c = names.index("gemm_packed_tile64_k16")
+                row.append((v, c))
+            table[t] = row
+        return table
+
+    square = {t: {} for t in TRANS}
+    skinny = [{t: {} for t in TRANS} for _ in range(3)]
+    for n in sizes:
+        for t in TRANS:
+            choice = measure(n, n, n, t, "square")
+            if n > 16:
+                square[t][n] = choice
+            else:
+                skinny[0][t][n] = choice   # m, n <= 16: the small table
+    if not args.square_only:
+        for s in [x for x in sizes if x > 16]:
+            for t in TRANS:
+                skinny[0][t][s] = measure(4, 4, s, t, "m=n=4")
+                skinny[1][t][s] = measure(4, s, s, t, "m=4")
+                skinny[2][t][s] = measure(s, 4, s, t, "n=4")
+    for t in TRANS:  # classes below every measured size take the smallest measured one
+        for d in [square] + skinny:
+            if not d[t]:
+                d[t] = {16: (3, -1)}
+    table = to_table(square)
+    sk = [to_table(skinny[c]) for c in range(3)]
     os.makedirs(args.out_dir, exist_ok=True)
     with open(os.path.join(args.out_dir, "gemm_tuned.h"), "w") as f:
-        f.write(header(table))
+        f.write(header(table, sk))
     with open(os.path.join(args.out_dir, "autotune.json"), "w") as f:
         json.dump({"configs": names, "results": results,
                    "time": time.strftime("%Y-%m-%d %H:%M:%S")}, f, indent=1)

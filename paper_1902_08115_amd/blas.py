@@ -14,7 +14,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import MbError, VARIANT_AUTO, VARIANT_DIRECT, VARIANT_PACKED  # noqa: F401
+from ._lib import MbError, VARIANT_AUTO, VARIANT_DIRECT, VARIANT_PACKED, VARIANT_REGTILE  # noqa: F401
 
 
 def _stream(stream) -> int:

@@ -32,14 +32,35 @@ struct Choice {
     int variant, config;
 };
 
-int size_class(int m, int n, int k)
+int dim_class(int mx)
 {
-    int mx = m > n ? m : n;
-    mx = mx > k ? mx : k;
     int e = 0;
     while (e < mb::kGemmTuneEntries - 1 && mx > mb::kGemmTuneMaxDim[e])
         ++e;
     return e;
+}
+
+int size_class(int m, int n, int k)
+{
+    int mx = m > n ? m : n;
+    return dim_class(mx > k ? mx : k);
+}
+
+// The table entry for a shape: results with both sides above 16 use the
+// square table (class of max(m, n, k)); thin (n <= 16), flat (m <= 16) and
+// small results use the skinny tables, so that the choice follows the
+// shape of C as the paper's variant switch does for rectangular matrices
+// (Sec. 2.3.2, App. C).
+const int *table_entry(int ta, int tb, int m, int n, int k)
+{
+    const int tc = 2 * ta + tb;
+    if (m > 16 && n > 16)
+        return mb::kGemmTune[tc][size_class(m, n, k)];
+    if (m <= 16 && n <= 16)
+        return mb::kGemmSkinny[0][tc][dim_class(k)];
+    if (m <= 16)
+        return mb::kGemmSkinny[1][tc][dim_class(n > k ? n : k)];
+    return mb::kGemmSkinny[2][tc][dim_class(m > k ? m : k)];
 }
 
 // A WAVE configuration holds a whole instance: fall back to the first TILE
@@ -54,8 +75,7 @@ int fit_config(int config, int m, int n)
 
 Choice select(int ta, int tb, int m, int n, int k, int variant)
 {
-    const int e = size_class(m, n, k);
-    const int *t = mb::kGemmTune[2 * ta + tb][e];
+    const int *t = table_entry(ta, tb, m, n, k);
     Choice c;
     c.variant = (variant == MB_VARIANT_AUTO) ? t[0] : variant;
     int cfg = t[1];
@@ -74,6 +94,15 @@ int select_variant(int ta, int tb, int m, int n, int k)
 }
 
 int to_status(hipError_t e) { return e == hipSuccess ? MB_OK : MB_ERR_HIP; }
+
+// The register-tile kernels address an operand with 32-bit byte offsets.
+bool regtile_fits(int ta, int tb, const GemmArgs &a)
+{
+    const int64_t lim = ((int64_t)1 << 32) / 8;
+    const int64_t acols = ta ? a.m : a.k, bcols = tb ? a.k : a.n;
+    return (int64_t)a.lda * acols < lim && (int64_t)a.ldb * bcols < lim &&
+           (int64_t)a.ldc * a.n < lim;
+}
 
 // Shared validation of the dgemm scalar arguments; positions of lda/ldb/ldc
 // differ between the call forms and are passed in.
@@ -105,7 +134,7 @@ int gemm_strided(char transa, char transb, int m, int n, int k, double alpha, co
     if (strideB < 0) return -12;
     if (strideC < 0) return -16;
     if (batch < 0) return -17;
-    if (variant < MB_VARIANT_AUTO || variant > MB_VARIANT_PACKED) return -pos_variant;
+    if (variant < MB_VARIANT_AUTO || variant > MB_VARIANT_REGTILE) return -pos_variant;
     if (batch > 1 && m > 0 && n > 0 && strideC < (int64_t)ldc * (n - 1) + m) return -16;
     const bool work = m > 0 && n > 0 && batch > 0 && !((alpha == 0.0 || k == 0) && beta == 1.0);
     if (work) {
@@ -132,7 +161,7 @@ int gemm_array(char transa, char transb, int m, int n, int k, double alpha,
     if (st != MB_OK)
         return st;
     if (batch < 0) return -14;
-    if (variant < MB_VARIANT_AUTO || variant > MB_VARIANT_PACKED) return -pos_variant;
+    if (variant < MB_VARIANT_AUTO || variant > MB_VARIANT_REGTILE) return -pos_variant;
     const bool work = m > 0 && n > 0 && batch > 0 && !((alpha == 0.0 || k == 0) && beta == 1.0);
     if (work) {
         const bool reads_ab = alpha != 0.0 && k > 0;
@@ -176,6 +205,10 @@ int run_gemm(int ta, int tb, GemmArgs &a, int variant, int config, hipStream_t s
     const Choice c = select(ta, tb, a.m, a.n, a.k, variant);
     if (c.variant == MB_VARIANT_DIRECT)
         return to_status(mb::launch_gemm_direct(ta, tb, a, s));
+    if (c.variant == MB_VARIANT_REGTILE && regtile_fits(ta, tb, a))
+        return to_status(mb::launch_gemm_regtile(ta, tb, a.m > 16 ? 2 : 1, a.n > 16 ? 2 : 1, a, s));
+    if (c.variant == MB_VARIANT_REGTILE)  // an operand too large for 32-bit offsets
+        return to_status(mb::launch_gemm_packed_config(3, ta, tb, a, s));
     return to_status(mb::launch_gemm_packed_config(c.config, ta, tb, a, s));
 }
 
@@ -295,6 +328,11 @@ const char *mb_dgemm_kernel_name(char transa, char transb, int m, int n, int k, 
     const Choice c = select(ta, tb, m, n, k, variant);
     if (c.variant == MB_VARIANT_DIRECT)
         return "gemm_direct";
+    if (c.variant == MB_VARIANT_REGTILE) {
+        static const char *names[4] = {"gemm_regtile_t11", "gemm_regtile_t21", "gemm_regtile_t12",
+                                       "gemm_regtile_t22"};
+        return names[(m > 16 ? 1 : 0) + (n > 16 ? 2 : 0)];
+    }
     return mb::packed_config_name(c.config);
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace mb {
 
 // One batched dgemm call, already validated.  Instance b of X is
@@ -172,6 +174,10 @@ hipError_t launch_gemm_direct(bool ta, bool tb, const GemmArgs &a, hipStream_t s
 hipError_t launch_gemm_packed_config(int config, bool ta, bool tb, const GemmArgs &a,
                                      hipStream_t s);
 hipError_t launch_gemm_scale(const GemmArgs &a, hipStream_t s);
+// Register tiles of tm x tn (1 or 2) MFMA blocks; every instance must span
+// less than 4 GiB per operand (32-bit offsets).
+hipError_t launch_gemm_regtile(bool ta, bool tb, int tm, int tn, const GemmArgs &a,
+                               hipStream_t s);
 hipError_t launch_potrf_lower(const PotrfArgs &a, hipStream_t s);
 hipError_t launch_fill_info(int *info, int batch, hipStream_t s);
 hipError_t launch_potrf_adj(const PotrfAdjArgs &a, hipStream_t s);

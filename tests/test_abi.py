@@ -251,3 +251,18 @@ def test_plan_options_errors(L):
     assert L.lib.mb_plan_create_ex(vp(arr), 1, None, None, None) == -4
     st, hd, idx = L.plan_create(arr, tile_two_min=32, potrf_waves=2)
     assert (st, hd, idx) == (L.MB_ERR_INVALID_PROBLEM, None, 0)
+
+
+def test_variant_range_and_skinny_dispatch(L):
+    """Forced families 0..3 are accepted, 4 is not (position 18 of the _ex
+    call); the shape-aware dispatch names a kernel for thin, flat and small
+    results without a GPU."""
+    base = ("N", "N", 4, 4, 4, 1.0, P, 4, 16, P, 4, 16, 1.0, P, 4, 16, 0)
+    assert L.dgemm_strided_batched(*base, 0, L.VARIANT_REGTILE) == 0  # batch 0: quick return
+    assert L.dgemm_strided_batched(*base, 0, 4) == -18
+    for (m, n, k) in ((4, 300, 300), (300, 4, 300), (4, 4, 300), (300, 300, 300)):
+        name = L.dgemm_kernel_name("T", "N", m, n, k)
+        assert name.startswith("gemm_"), name
+    assert L.dgemm_kernel_name("N", "N", 4, 300, 300, L.VARIANT_REGTILE) == "gemm_regtile_t12"
+    assert L.dgemm_kernel_name("N", "N", 300, 4, 300, L.VARIANT_REGTILE) == "gemm_regtile_t21"
+    assert L.dgemm_select("N", "N", 4, 300, 300) in (1, 2, 3)

@@ -16,7 +16,7 @@ from tests.gpu_util import (GEMM_TOL, dev, gemm_dims, gemm_errors, host, oracle_
 pytestmark = pytest.mark.gpu
 
 TRANS = ["NN", "NT", "TN", "TT"]
-VARIANTS = {"direct": 1, "packed": 2, "auto": 0}
+VARIANTS = {"direct": 1, "packed": 2, "auto": 0, "regtile": 3}
 
 
 def _make(g, ta, tb, m, n, k, batch, pad=0, gap=0, integer=False):
@@ -62,7 +62,7 @@ EXACT_SHAPES = [(1, 1, 1), (4, 4, 4), (5, 7, 3), (8, 8, 8), (13, 9, 21), (16, 16
                 (130, 70, 129)]
 
 
-@pytest.mark.parametrize("variant", ["direct", "packed", "auto"])
+@pytest.mark.parametrize("variant", ["direct", "packed", "auto", "regtile"])
 @pytest.mark.parametrize("trans", TRANS)
 def test_integer_exact(trans, variant):
     """Integer entries in [-4, 4]: every partial sum is exact, so the GPU result
@@ -83,7 +83,7 @@ def test_integer_exact(trans, variant):
         assert np.array_equal(Cg, Cr, equal_nan=True), f"m={m} n={n} k={k}"
 
 
-@pytest.mark.parametrize("variant", ["direct", "packed"])
+@pytest.mark.parametrize("variant", ["direct", "packed", "regtile"])
 @pytest.mark.parametrize("trans", TRANS)
 def test_random_sweep_sizes(trans, variant):
     """U[-1,1) data at every sweep size (small batch): both error gates."""
@@ -122,7 +122,7 @@ def test_batched_equals_single_calls(trans):
         assert np.array_equal(Cb, Cs, equal_nan=True)
 
 
-@pytest.mark.parametrize("variant", ["direct", "packed", "auto"])
+@pytest.mark.parametrize("variant", ["direct", "packed", "auto", "regtile"])
 def test_pointer_array_equals_strided(variant):
     torch, _lib, _ = torch_mods()
     g = inputs.rng(7200)
@@ -264,3 +264,35 @@ def test_every_packed_config_exact():
     # a WAVE configuration refuses an instance larger than its tile
     assert _lib.dgemm_strided_batched_config("N", "N", 17, 17, 4, 1.0, 16, 17, 289, 16, 4, 68,
                                              0.0, 16, 17, 289, 1, 0, s) == _lib.MB_ERR_UNSUPPORTED
+
+
+SKINNY = [(4, 4, 1), (4, 4, 2), (4, 4, 3), (4, 4, 17), (4, 4, 300), (1, 300, 5), (4, 300, 300),
+          (4, 37, 200), (16, 17, 33), (300, 4, 300), (97, 4, 15), (17, 16, 9), (3, 5, 300),
+          (16, 16, 257), (33, 2, 64)]
+
+
+@pytest.mark.parametrize("variant", ["auto", "regtile"])
+@pytest.mark.parametrize("trans", TRANS)
+def test_skinny_shapes(trans, variant):
+    """Thin, flat and small results with long and short k (the paper's skinny
+    sweeps, App. C, plus ragged edges): bit-exact on integer data, NaN ld
+    padding untouched, both through the shape-aware dispatch and forced onto
+    the register-tile kernels."""
+    ta, tb = trans
+    g = inputs.rng(7700 + TRANS.index(trans))
+    for (m, n, k), (alpha, beta) in zip(SKINNY, itertools.cycle([(1.0, 1.0), (-2.0, 0.5),
+                                                                  (1.0, 0.0)])):
+        A, B, C = _make(g, ta, tb, m, n, k, 3, pad=1, gap=1, integer=True)
+        if beta == 0.0:
+            C[:, :, :m] = np.nan
+        say(f"dgemm skinny {trans} {variant} m={m} n={n} k={k} "
+            f"[{_lib_name(ta, tb, m, n, k)}]")
+        Cg = _run_strided(ta, tb, m, n, k, alpha, A, B, beta, C, 3, VARIANTS[variant])
+        Cr = oracle_gemm_batch(ta, tb, m, n, k, alpha, A, A.shape[2], B, B.shape[2], beta, C,
+                               C.shape[2], 3)
+        assert np.array_equal(Cg, Cr, equal_nan=True), f"m={m} n={n} k={k}"
+
+
+def _lib_name(ta, tb, m, n, k):
+    from paper_1902_08115_amd import _lib
+    return _lib.dgemm_kernel_name(ta, tb, m, n, k)
