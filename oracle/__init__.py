@@ -72,6 +72,17 @@ def _declare(lib):
     lib.oracle_dpotrf_l_adjoint_strided_batched.argtypes = [c_int, vp, c_int, c_i64, vp, c_int,
                                                             c_i64, vp, c_int, c_i64, c_int, c_int]
     lib.oracle_dpotrf_l_adjoint_strided_batched.restype = c_int
+    lib.oracle_dtrmm_rlnn.argtypes = [c_int, c_int, c_double, vp, c_int, vp, c_int]
+    lib.oracle_dtrmm_rlnn.restype = None
+    lib.oracle_dsyrk_ln.argtypes = [c_int, c_int, c_double, vp, c_int, c_double, vp, c_int]
+    lib.oracle_dsyrk_ln.restype = None
+    lib.oracle_riccati.argtypes = [c_int, c_int, c_int, vp, c_int, c_i64, vp, c_int, c_i64,
+                                   vp, c_int, vp, c_int, c_i64, vp, c_int, vp]
+    lib.oracle_riccati.restype = c_int
+    lib.oracle_riccati_strided_batched.argtypes = [
+        c_int, c_int, c_int, vp, c_int, c_i64, c_i64, vp, c_int, c_i64, c_i64, vp, c_int, c_i64,
+        vp, c_int, c_i64, c_i64, vp, c_int, c_i64, vp, c_int, c_int]
+    lib.oracle_riccati_strided_batched.restype = c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = c_int
 
@@ -94,7 +105,7 @@ def _storage(x: np.ndarray, name: str):
     if x.ndim != 2:
         raise ValueError(f"{name} must be 2-D")
     s0, s1 = x.strides
-    if x.shape[0] > 0 and x.shape[1] > 1 and s0 != 8:
+    if x.shape[0] > 1 and x.shape[1] > 1 and s0 != 8:
         raise ValueError(f"{name} must be column-major (unit row stride)")
     ld = s1 // 8 if x.shape[1] > 1 else max(1, x.shape[0])
     return ld
@@ -181,6 +192,70 @@ def dpotrf_l_adjoint_strided_batched(n, L, ldl, strideL, Lbar, ldlb, strideLb, A
                                                      nthreads)
     if rc != 0:
         raise MemoryError("oracle_dpotrf_l_adjoint_strided_batched: allocation failed")
+
+
+def dtrmm_rlnn(alpha: float, A: np.ndarray, B: np.ndarray, lib=None) -> None:
+    """B <= alpha * B * tril(A) in place (dtrmm 'R','L','N','N'; Sec. 3.1.4, Sec. 5.2)."""
+    lib = lib or load()
+    m, n = B.shape
+    if A.shape[0] < n or A.shape[1] < n:
+        raise ValueError("A must be at least n x n")
+    lib.oracle_dtrmm_rlnn(m, n, float(alpha), _ptr(A), _storage(A, "A"), _ptr(B),
+                          _storage(B, "B"))
+
+
+def dsyrk_ln(alpha: float, A: np.ndarray, beta: float, C: np.ndarray, lib=None) -> None:
+    """Lower triangle of C <= alpha * A * A^T + beta * C in place (dsyrk 'L','N';
+    Sec. 3.1.2, Sec. 5.2)."""
+    lib = lib or load()
+    n, k = A.shape
+    if C.shape != (n, n):
+        raise ValueError("C must be n x n")
+    lib.oracle_dsyrk_ln(n, k, float(alpha), _ptr(A), _storage(A, "A"), float(beta), _ptr(C),
+                        _storage(C, "C"))
+
+
+def riccati(BAt: np.ndarray, RSQ: np.ndarray, QN: np.ndarray, nu: int, lib=None):
+    """Factorized backward Riccati recursion of Sec. 5.2 for one problem.
+
+    BAt: (N, m, nx) stage matrices [B^T; A^T]; RSQ: (N, m, m) stage matrices
+    [R S; S^T Q] (lower triangle read); QN: (nx, nx).  Returns (F, LN, info)
+    with F (N, m, m) the stage factors (lower triangles written, the rest
+    zero), LN = chol(QN) and info (N + 1,) as documented in oracle.c."""
+    lib = lib or load()
+    N, m, nx = BAt.shape
+    if m != nu + nx or RSQ.shape != (N, m, m) or QN.shape != (nx, nx):
+        raise ValueError("inconsistent Riccati shapes")
+    # column-major stage matrices: element (i, j) of stage n at n*m*c + j*m + i
+    bat = np.ascontiguousarray(np.swapaxes(BAt, 1, 2), dtype=np.float64)
+    rsq = np.ascontiguousarray(np.swapaxes(RSQ, 1, 2), dtype=np.float64)
+    q = np.asfortranarray(QN, dtype=np.float64)
+    F = np.zeros((max(N, 1), m, m), dtype=np.float64)
+    LN = np.zeros((nx, nx), dtype=np.float64, order="F")
+    info = np.zeros(N + 1, dtype=np.int32)
+    rc = lib.oracle_riccati(nx, nu, N, _ptr(bat), max(m, 1), m * nx, _ptr(rsq), max(m, 1), m * m,
+                            _ptr(q), max(nx, 1), _ptr(F), max(m, 1), m * m, _ptr(LN), max(nx, 1),
+                            _ptr(info))
+    if rc != 0:
+        raise MemoryError("oracle_riccati: allocation failed")
+    return np.swapaxes(F[:N], 1, 2).copy(), np.array(LN), info
+
+
+def riccati_strided_batched(nx, nu, N, BAt, ldbat, sbat, strideBAt, RSQ, ldrsq, srsq, strideRSQ,
+                            QN, ldq, strideQ, F, ldf, sf, strideF, LN, ldl, strideL, info, batch,
+                            nthreads=0, lib=None):
+    """Batched form on flat buffers (stage stride s*, problem stride stride*)."""
+    lib = lib or load()
+    for nm, a in (("BAt", BAt), ("RSQ", RSQ), ("QN", QN), ("F", F), ("LN", LN)):
+        _check_f64(a, nm)
+    if info.dtype != np.int32:
+        raise TypeError("info must be int32")
+    rc = lib.oracle_riccati_strided_batched(nx, nu, N, _ptr(BAt), ldbat, sbat, strideBAt,
+                                            _ptr(RSQ), ldrsq, srsq, strideRSQ, _ptr(QN), ldq,
+                                            strideQ, _ptr(F), ldf, sf, strideF, _ptr(LN), ldl,
+                                            strideL, _ptr(info), batch, nthreads)
+    if rc != 0:
+        raise MemoryError("oracle_riccati_strided_batched: allocation failed")
 
 
 def num_threads(lib=None) -> int:

@@ -1,6 +1,7 @@
 /*
  * oracle.c -- plain, slow, obviously correct CPU reference for the batched
- * small-matrix FP64 dgemm / dpotrf('L') path.
+ * small-matrix FP64 dgemm / dpotrf('L') path and the Riccati recursion built
+ * from dtrmm, dsyrk and dpotrf.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
  * calls this file; only the test suite, the smoke check and the CPU-baseline
@@ -28,6 +29,17 @@
  *   oracle_dpotrf_l_adjoint     -- not in the paper; reverse-mode derivative
  *                                  of the lower Cholesky factor (S. P. Smith,
  *                                  1995; I. Murray, arXiv:1602.07527, 2016).
+ *   oracle_dtrmm_rlnn           -- Sec. 3.1.4 and Sec. 5.2 (BLAS dtrmm
+ *                                  with side 'R', uplo 'L', trans 'N', diag
+ *                                  'N': B <= alpha * B * A, A lower).  Plain
+ *                                  definition.
+ *   oracle_dsyrk_ln             -- Sec. 3.1.2 and Sec. 5.2 (BLAS dsyrk with
+ *                                  uplo 'L', trans 'N': lower triangle of
+ *                                  C <= alpha * A * A^T + beta * C).  Plain
+ *                                  definition.
+ *   oracle_riccati              -- Sec. 5.2, the factorized backward Riccati
+ *                                  recursion: per stage one dtrmm_rlnn, one
+ *                                  dsyrk_ln and one dpotrf_l, in that order.
  *   *_strided_batched           -- independent instances, OpenMP over
  *                                  instances, each instance single-threaded
  *                                  (the paper evaluates single-threaded
@@ -234,6 +246,142 @@ int oracle_dpotrf_l_adjoint_strided_batched(int n, const double *L, int ldl, int
         bad |= oracle_dpotrf_l_adjoint(n, L + (ptrdiff_t)b * strideL, ldl,
                                        Lbar + (ptrdiff_t)b * strideLb, ldlb,
                                        Abar + (ptrdiff_t)b * strideAb, ldab) != 0;
+    (void)nthreads;
+    return bad ? -1 : 0;
+}
+
+/*
+ * B <= alpha * B * A, B m x n, A n x n lower triangular with its diagonal
+ * (dtrmm side 'R', uplo 'L', trans 'N', diag 'N').  Entry (i, j) of B * A is
+ * sum_{p=j}^{n-1} b_ip * a_pj, summed in increasing p (A's strictly upper
+ * part is never read).  Columns are produced in increasing j: column j reads
+ * only columns p >= j of B, none of which has been overwritten yet.
+ */
+void oracle_dtrmm_rlnn(int m, int n, double alpha, const double *A, int lda, double *B, int ldb)
+{
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < m; ++i) {
+            double s = 0.0;
+            for (int p = j; p < n; ++p)
+                s += B[(size_t)i + (size_t)p * (size_t)ldb] * A[(size_t)p + (size_t)j * (size_t)lda];
+            B[(size_t)i + (size_t)j * (size_t)ldb] = alpha * s;
+        }
+}
+
+/*
+ * Lower triangle of C <= alpha * A * A^T + beta * C, C n x n, A n x k
+ * (dsyrk uplo 'L', trans 'N').  For i >= j, s_ij = sum_{p<k} a_ip * a_jp in
+ * increasing p, and c_ij <= alpha * s_ij + beta * c_ij (beta == 0: C not
+ * read).  The scalar special cases are those of oracle_dgemm.  The strictly
+ * upper triangle of C is never touched.
+ */
+void oracle_dsyrk_ln(int n, int k, double alpha, const double *A, int lda, double beta,
+                     double *C, int ldc)
+{
+    if (n == 0)
+        return;
+    if ((alpha == 0.0 || k == 0) && beta == 1.0)
+        return;
+    for (int j = 0; j < n; ++j)
+        for (int i = j; i < n; ++i) {
+            double *c = &C[(size_t)i + (size_t)j * (size_t)ldc];
+            if (k == 0 || alpha == 0.0) {
+                *c = (beta == 0.0) ? 0.0 : beta * (*c);
+                continue;
+            }
+            double acc = 0.0;
+            for (int p = 0; p < k; ++p)
+                acc += A[(size_t)i + (size_t)p * (size_t)lda] * A[(size_t)j + (size_t)p * (size_t)lda];
+            if (beta == 0.0)
+                *c = alpha * acc;
+            else
+                *c = alpha * acc + beta * (*c);
+        }
+}
+
+/*
+ * One backward Riccati recursion in the factorized form of Sec. 5.2, for a
+ * system with nx states, nu controls and horizon N (m = nu + nx):
+ *   Lc_N = chol(Q_N)                                      (dpotrf_l)
+ *   for n = N-1 down to 0:
+ *     C_n  = BAt_n * Lc_{n+1}        m x nx               (dtrmm_rlnn)
+ *     F_n  = RSQ_n + C_n * C_n^T     lower triangle       (dsyrk_ln)
+ *     F_n  = chol(F_n) = [Lambda_n 0; L_n Lc_n]           (dpotrf_l)
+ *     Lc_n = F_n(nu:m, nu:m), the lower factor of P_n
+ * with BAt_n = [B_n^T; A_n^T] (m x nx) and RSQ_n = [R_n S_n; S_n^T Q_n]
+ * (m x m, symmetric, lower triangle read).  Stage n of X is at
+ * X + n * sX within the problem.  Outputs: the lower triangles of F_n
+ * (ldf) and of LN = Lc_N (ldl); their strictly upper parts are not touched.
+ * info[N] is the dpotrf info of Q_N, info[n] that of stage n; a failed
+ * factorization stops the recursion, and the stages below it are not
+ * computed (F_n untouched, info[n] = -1).
+ * Returns 0, or -1 when the work buffer cannot be allocated.
+ */
+int oracle_riccati(int nx, int nu, int N,
+                   const double *BAt, int ldbat, int64_t sbat,
+                   const double *RSQ, int ldrsq, int64_t srsq,
+                   const double *QN, int ldq,
+                   double *F, int ldf, int64_t sf,
+                   double *LN, int ldl, int *info)
+{
+    const int m = nu + nx;
+    for (int n = 0; n <= N; ++n)
+        info[n] = -1;
+    for (int j = 0; j < nx; ++j)
+        for (int i = j; i < nx; ++i)
+            LN[(size_t)i + (size_t)j * (size_t)ldl] = QN[(size_t)i + (size_t)j * (size_t)ldq];
+    info[N] = oracle_dpotrf_l(nx, LN, ldl);
+    if (info[N] != 0 || N == 0)
+        return 0;
+    double *C = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * (size_t)(nx > 0 ? nx : 1));
+    if (!C)
+        return -1;
+    const double *Lc = LN;
+    int ldlc = ldl;
+    for (int n = N - 1; n >= 0; --n) {
+        const double *Bn = BAt + (ptrdiff_t)n * sbat;
+        const double *Rn = RSQ + (ptrdiff_t)n * srsq;
+        double *Fn = F + (ptrdiff_t)n * sf;
+        for (int j = 0; j < nx; ++j)
+            for (int i = 0; i < m; ++i)
+                C[(size_t)i + (size_t)j * (size_t)m] = Bn[(size_t)i + (size_t)j * (size_t)ldbat];
+        oracle_dtrmm_rlnn(m, nx, 1.0, Lc, ldlc, C, m);
+        for (int j = 0; j < m; ++j)
+            for (int i = j; i < m; ++i)
+                Fn[(size_t)i + (size_t)j * (size_t)ldf] = Rn[(size_t)i + (size_t)j * (size_t)ldrsq];
+        oracle_dsyrk_ln(m, nx, 1.0, C, m, 1.0, Fn, ldf);
+        info[n] = oracle_dpotrf_l(m, Fn, ldf);
+        if (info[n] != 0)
+            break;
+        Lc = Fn + (size_t)nu + (size_t)nu * (size_t)ldf;
+        ldlc = ldf;
+    }
+    free(C);
+    return 0;
+}
+
+/* Problem b uses X + b * strideX for every operand and info + b * (N + 1). */
+int oracle_riccati_strided_batched(int nx, int nu, int N,
+                                   const double *BAt, int ldbat, int64_t sbat, int64_t strideBAt,
+                                   const double *RSQ, int ldrsq, int64_t srsq, int64_t strideRSQ,
+                                   const double *QN, int ldq, int64_t strideQ,
+                                   double *F, int ldf, int64_t sf, int64_t strideF,
+                                   double *LN, int ldl, int64_t strideL,
+                                   int *info, int batch, int nthreads)
+{
+    int bad = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic) num_threads(nthreads) reduction(| : bad)
+#endif
+    for (int b = 0; b < batch; ++b)
+        bad |= oracle_riccati(nx, nu, N, BAt + (ptrdiff_t)b * strideBAt, ldbat, sbat,
+                              RSQ + (ptrdiff_t)b * strideRSQ, ldrsq, srsq,
+                              QN + (ptrdiff_t)b * strideQ, ldq,
+                              F + (ptrdiff_t)b * strideF, ldf, sf,
+                              LN + (ptrdiff_t)b * strideL, ldl,
+                              info + (ptrdiff_t)b * (N + 1)) != 0;
     (void)nthreads;
     return bad ? -1 : 0;
 }

@@ -16,7 +16,13 @@ What pins what (all CPU, no GPU):
     the Pascal and 3x3 textbook fixtures, the 1x1/2x2 closed forms, the
     reconstruction residual, untouched upper triangle;
   * Cholesky adjoint: log-det closed form (Abar = A^-1), n = 1, central finite
-    differences.
+    differences;
+  * dtrmm_rlnn / dsyrk_ln: exact rational brute force with NaN sentinels in
+    the parts that must not be read or written, SciPy/OpenBLAS dtrmm and dsyrk;
+  * Riccati recursion: the closed-form update of Sec. 5.2 (solved with a
+    general linear solve, not a Cholesky factorization), the scalar closed
+    form, convergence to SciPy's discrete algebraic Riccati solution on a long
+    horizon, the info and not-computed-stage rules, batched == single.
 """
 from __future__ import annotations
 
@@ -459,6 +465,252 @@ def pin_adjoint_finite_differences(lib, seed=32, h=1e-6):
             assert abs(fd - an) <= 1e-6 * (abs(fd) + 1e-300) + 1e-9, f"n={n}: fd {fd} vs {an}"
 
 
+# ---------------------------------------------------------------- dtrmm / dsyrk
+
+
+def pin_trmm_exact_bruteforce(lib, seed=41):
+    """B <= alpha * B * tril(A): exact integer results, A's upper part and B's
+    padding rows hold NaN sentinels that must be neither read nor written."""
+    g = _rng(seed)
+    for m in range(0, 5):
+        for n in range(0, 5):
+            for alpha in (1.0, -2.0, 0.5):
+                A = np.full((n + 2, max(n, 1)), np.nan, order="F")
+                for j in range(n):
+                    for i in range(j, n):
+                        A[i, j] = float(g.integers(-4, 5))
+                B, ldb = _colmajor_padded(g, m, n, 2)
+                B0 = B.copy(order="F")
+                lib.oracle_dtrmm_rlnn(m, n, alpha, oracle._ptr(A), n + 2, oracle._ptr(B), ldb)
+                for i in range(m):
+                    for j in range(n):
+                        exact = Fraction(alpha) * sum(Fraction(B0[i, p]) * Fraction(A[p, j])
+                                                      for p in range(j, n))
+                        assert B[i, j] == float(exact), (m, n, alpha, i, j)
+                assert np.all(np.isnan(B[m:, :])), "padding rows of B written"
+
+
+def pin_syrk_exact_bruteforce(lib, seed=42):
+    """Lower triangle of alpha * A A^T + beta * C exactly; the strictly upper
+    triangle (NaN) untouched; beta == 0 does not read C."""
+    g = _rng(seed)
+    for n in range(0, 5):
+        for k in range(0, 5):
+            for alpha, beta in ((1.0, 1.0), (-1.0, 2.0), (2.0, 0.0), (0.0, 3.0), (1.0, 0.0)):
+                A, lda = _colmajor_padded(g, n, k, 1)
+                C = np.full((n + 1, max(n, 1)), np.nan, order="F")
+                for j in range(n):
+                    for i in range(j, n):
+                        C[i, j] = np.nan if beta == 0.0 else float(g.integers(-4, 5))
+                C0 = C.copy(order="F")
+                lib.oracle_dsyrk_ln(n, k, alpha, oracle._ptr(A), lda, beta, oracle._ptr(C), n + 1)
+                for j in range(n):
+                    for i in range(n):
+                        if i < j:
+                            assert np.isnan(C[i, j]), "upper triangle written"
+                            continue
+                        s = sum(Fraction(A[i, p]) * Fraction(A[j, p]) for p in range(k))
+                        exact = Fraction(alpha) * s
+                        if beta != 0.0:
+                            exact += Fraction(beta) * Fraction(C0[i, j])
+                        if (alpha == 0.0 or k == 0) and beta == 1.0:
+                            exact = Fraction(C0[i, j])
+                        assert C[i, j] == float(exact), (n, k, alpha, beta, i, j)
+
+
+def pin_trmm_syrk_scipy(lib, seed=43):
+    """Against SciPy's BLAS dtrmm (side R, lower, no-trans, non-unit) and dsyrk
+    (lower, no-trans), an independent library."""
+    from scipy.linalg import blas
+    g = _rng(seed)
+    for m, n in ((7, 5), (1, 9), (33, 17), (12, 1)):
+        A = np.asfortranarray(g.uniform(-1, 1, size=(n, n)))
+        B = np.asfortranarray(g.uniform(-1, 1, size=(m, n)))
+        ref = blas.dtrmm(0.75, A, B, side=1, lower=1, trans_a=0, diag=0)
+        got = B.copy(order="F")
+        oracle.dtrmm_rlnn(0.75, A, got, lib=lib)
+        assert np.max(np.abs(got - ref)) <= 1e-14 * max(1.0, np.max(np.abs(ref))) * n
+    for n, k in ((6, 4), (1, 7), (31, 9), (9, 1)):
+        A = np.asfortranarray(g.uniform(-1, 1, size=(n, k)))
+        C = np.asfortranarray(g.uniform(-1, 1, size=(n, n)))
+        ref = blas.dsyrk(-0.5, A, beta=1.5, c=C, trans=0, lower=1)
+        got = C.copy(order="F")
+        oracle.dsyrk_ln(-0.5, A, 1.5, got, lib=lib)
+        lo = np.tril_indices(n)
+        assert np.max(np.abs(got[lo] - ref[lo])) <= 1e-14 * max(1.0, np.max(np.abs(ref))) * k
+        up = np.triu_indices(n, 1)
+        assert np.array_equal(got[up], C[up])
+
+
+# ---------------------------------------------------------------- Riccati
+
+
+def _riccati_problem(g, nx, nu, N, rho=None):
+    """Stage data with [R S; S^T Q] SPD and BAt = [B^T; A^T]; rho scales A."""
+    m = nu + nx
+    BAt = g.uniform(-1, 1, size=(N, m, nx)) / math.sqrt(max(nx, 1))
+    if rho is not None:
+        BAt[:, nu:, :] *= rho
+    W = g.uniform(-1, 1, size=(N, m, m))
+    RSQ = W @ np.swapaxes(W, 1, 2) / m + np.eye(m)
+    V = g.uniform(-1, 1, size=(nx, nx))
+    QN = V @ V.T / max(nx, 1) + np.eye(nx)
+    return BAt, RSQ, QN
+
+
+def _split(BAt_n, RSQ_n, nu):
+    B = BAt_n[:nu, :].T          # nx x nu
+    A = BAt_n[nu:, :].T          # nx x nx
+    R = RSQ_n[:nu, :nu]
+    S = np.tril(RSQ_n)[nu:, :nu].T   # nu x nx (lower triangle is the stored part)
+    Q = RSQ_n[nu:, nu:]
+    Q = np.tril(Q) + np.tril(Q, -1).T
+    return A, B, R, S, Q
+
+
+def pin_riccati_closed_form(lib, seed=44):
+    """Every stage: Lc_n Lc_n^T equals the Riccati update
+    Q + A^T P A - (S^T + A^T P B)(R + B^T P B)^{-1}(S + B^T P A) with
+    P = Lc_{n+1} Lc_{n+1}^T (a general solve, not a Cholesky), and the other
+    blocks of the stage factor satisfy Lambda Lambda^T = R + B^T P B,
+    L_n Lambda^T = S^T + A^T P B.  Also Lc_N Lc_N^T = Q_N."""
+    g = _rng(seed)
+    for nx, nu, N in ((1, 1, 3), (3, 2, 4), (8, 4, 10), (5, 0, 3), (17, 9, 5), (24, 12, 3)):
+        BAt, RSQ, QN = _riccati_problem(g, nx, nu, N)
+        F, LN, info = oracle.riccati(BAt, RSQ, QN, nu, lib=lib)
+        assert np.all(info == 0)
+        assert np.allclose(np.triu(LN, 1), 0.0) and np.allclose(np.triu(F, 1), 0.0)
+        assert np.max(np.abs(LN @ LN.T - QN)) <= 1e-13 * np.max(np.abs(QN))
+        Lc = LN
+        for n in range(N - 1, -1, -1):
+            A, B, R, S, Q = _split(BAt[n], RSQ[n], nu)
+            P = Lc @ Lc.T
+            Fn = F[n]
+            Lam, Ln, Lcn = Fn[:nu, :nu], Fn[nu:, :nu], Fn[nu:, nu:]
+            if nu > 0:
+                Re = R + B.T @ P @ B
+                Ge = S.T + A.T @ P @ B
+                Pn = Q + A.T @ P @ A - Ge @ np.linalg.solve(Re, Ge.T)
+                assert np.max(np.abs(Lam @ Lam.T - Re)) <= 1e-12 * np.max(np.abs(Re))
+                assert np.max(np.abs(Ln @ Lam.T - Ge)) <= 1e-12 * np.max(np.abs(Ge))
+            else:
+                Pn = Q + A.T @ P @ A
+            err = np.max(np.abs(Lcn @ Lcn.T - Pn)) / np.max(np.abs(Pn))
+            assert err <= 1e-12, (nx, nu, n, err)
+            Lc = Lcn
+
+
+def pin_riccati_scalar(lib):
+    """nx = nu = 1: p_n = q + a^2 p - (s + a p b)^2 / (r + b^2 p), Lc_n = sqrt(p_n)."""
+    a, b, q, r, s, qN, N = 0.9, 0.7, 1.3, 0.8, 0.2, 2.0, 6
+    BAt = np.array([[[b], [a]]] * N)
+    RSQ = np.array([[[r, s], [s, q]]] * N)
+    F, LN, info = oracle.riccati(BAt, RSQ, np.array([[qN]]), 1, lib=lib)
+    assert np.all(info == 0)
+    p = qN
+    assert abs(LN[0, 0] - math.sqrt(p)) <= 1e-15 * math.sqrt(p)
+    for n in range(N - 1, -1, -1):
+        lam = math.sqrt(r + b * b * p)
+        l = (s + a * p * b) / lam
+        p = q + a * a * p - (s + a * p * b) ** 2 / (r + b * b * p)
+        assert abs(F[n][0, 0] - lam) <= 4e-16 * lam
+        assert abs(F[n][1, 0] - l) <= 8e-16 * abs(l)
+        assert abs(F[n][1, 1] - math.sqrt(p)) <= 8e-16 * math.sqrt(p), n
+
+
+def pin_riccati_dare_limit(lib, seed=45):
+    """Time-invariant stages over a long horizon: P_0 converges to the
+    stabilizing solution of the discrete algebraic Riccati equation
+    (SciPy's solve_discrete_are, s = the cross term S^T)."""
+    from scipy.linalg import solve_discrete_are
+    g = _rng(seed)
+    for nx, nu in ((4, 2), (6, 3)):
+        BAt1, RSQ1, _ = _riccati_problem(g, nx, nu, 1, rho=0.6)
+        N = 120
+        BAt = np.repeat(BAt1, N, axis=0)
+        RSQ = np.repeat(RSQ1, N, axis=0)
+        A, B, R, S, Q = _split(BAt1[0], RSQ1[0], nu)
+        F, LN, info = oracle.riccati(BAt, RSQ, np.eye(nx), nu, lib=lib)
+        assert np.all(info == 0)
+        Lc = F[0][nu:, nu:]
+        X = solve_discrete_are(A, B, Q, R, s=S.T)
+        assert np.max(np.abs(Lc @ Lc.T - X)) <= 1e-10 * np.max(np.abs(X)), (nx, nu)
+
+
+def pin_riccati_info(lib, seed=46):
+    """A stage whose matrix is not positive definite at column j reports
+    info = j + 1 there; the stages after it in the recursion (lower n) are not
+    computed (info -1, F untouched); a bad Q_N stops everything."""
+    g = _rng(seed)
+    nx, nu, N = 5, 3, 6
+    m = nx + nu
+    for fail_stage, j in ((3, 0), (0, 6), (5, 2)):
+        BAt, RSQ, QN = _riccati_problem(g, nx, nu, N)
+        RSQ[fail_stage] = np.diag(np.arange(1.0, m + 1))
+        RSQ[fail_stage][j, j] = -1.0
+        BAt[fail_stage][j, :] = 0.0
+        bat = np.ascontiguousarray(np.swapaxes(BAt, 1, 2))
+        rsq = np.ascontiguousarray(np.swapaxes(RSQ, 1, 2))
+        q = np.asfortranarray(QN)
+        F = np.full((N, m, m), 7.0)
+        LN = np.zeros((nx, nx), order="F")
+        info = np.zeros(N + 1, dtype=np.int32)
+        lib.oracle_riccati(nx, nu, N, oracle._ptr(bat), m, m * nx, oracle._ptr(rsq), m, m * m,
+                           oracle._ptr(q), nx, oracle._ptr(F), m, m * m, oracle._ptr(LN), nx,
+                           oracle._ptr(info))
+        want = [-1] * fail_stage + [j + 1] + [0] * (N - fail_stage)
+        assert info.tolist() == want, (info.tolist(), want)
+        for n in range(fail_stage):
+            assert np.all(F[n] == 7.0), "stage after a failure was written"
+    BAt, RSQ, QN = _riccati_problem(g, nx, nu, N)
+    QN[2, 2] = -5.0
+    F, LN, info = oracle.riccati(BAt, RSQ, QN, nu, lib=lib)
+    assert info.tolist() == [-1] * N + [3]
+
+
+def pin_riccati_batched_matches_single(lib, seed=47):
+    """The batched wrapper with padded leading dimensions and problem strides
+    reproduces the single-problem results bit for bit."""
+    g = _rng(seed)
+    nx, nu, N, batch = 6, 3, 4, 3
+    m = nx + nu
+    ldb, ldr, ldq, ldf, ldl = m + 1, m + 2, nx + 3, m + 1, nx + 2
+    sb, sr, sf = ldb * nx + 5, ldr * m + 1, ldf * m + 3
+    BATS = np.zeros(batch * N * sb + 64)
+    RSQS = np.zeros(batch * N * sr + 64)
+    QS = np.zeros(batch * ldq * nx + 64)
+    probs = []
+    for b in range(batch):
+        BAt, RSQ, QN = _riccati_problem(g, nx, nu, N)
+        probs.append((BAt, RSQ, QN))
+        for n in range(N):
+            for j in range(nx):
+                o = b * N * sb + n * sb + j * ldb
+                BATS[o:o + m] = BAt[n][:, j]
+            for j in range(m):
+                o = b * N * sr + n * sr + j * ldr
+                RSQS[o:o + m] = RSQ[n][:, j]
+        for j in range(nx):
+            o = b * ldq * nx + j * ldq
+            QS[o:o + nx] = QN[:, j]
+    FS = np.zeros(batch * N * sf + 64)
+    LS = np.zeros(batch * ldl * nx + 64)
+    info = np.zeros(batch * (N + 1), dtype=np.int32)
+    oracle.riccati_strided_batched(nx, nu, N, BATS, ldb, sb, N * sb, RSQS, ldr, sr, N * sr, QS,
+                                   ldq, ldq * nx, FS, ldf, sf, N * sf, LS, ldl, ldl * nx, info,
+                                   batch, lib=lib)
+    assert np.all(info == 0)
+    for b, (BAt, RSQ, QN) in enumerate(probs):
+        F, LN, _ = oracle.riccati(BAt, RSQ, QN, nu, lib=lib)
+        for n in range(N):
+            for j in range(m):
+                o = b * N * sf + n * sf + j * ldf
+                assert np.array_equal(FS[o + j:o + m], F[n][j:, j])
+        for j in range(nx):
+            o = b * ldl * nx + j * ldl
+            assert np.array_equal(LS[o + j:o + nx], LN[j:, j])
+
+
 ALL_PINS = [
     pin_dgemm_exact_bruteforce,
     pin_dgemm_lowercase_and_conj_flags,
@@ -479,4 +731,12 @@ ALL_PINS = [
     pin_adjoint_logdet,
     pin_adjoint_n1,
     pin_adjoint_finite_differences,
+    pin_trmm_exact_bruteforce,
+    pin_syrk_exact_bruteforce,
+    pin_trmm_syrk_scipy,
+    pin_riccati_closed_form,
+    pin_riccati_scalar,
+    pin_riccati_dare_limit,
+    pin_riccati_info,
+    pin_riccati_batched_matches_single,
 ]

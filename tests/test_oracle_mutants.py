@@ -44,6 +44,22 @@ MUTANTS = [
      "for (int p = i + 1; p < n; ++p)\n                    v +="),
     ("adjoint_transposed_L", "v -= Lx(p, i) * Px(p, j);", "v -= Lx(i, p) * Px(p, j);"),
     ("adjoint_second_solve_sign", "v -= Px(r, p) * Lx(p, c);", "v += Px(r, p) * Lx(p, c);"),
+    ("trmm_reads_upper", "* A[(size_t)p + (size_t)j * (size_t)lda];\n            B[",
+     "* A[(size_t)j + (size_t)p * (size_t)lda];\n            B["),
+    ("trmm_dropped_diagonal", "for (int p = j; p < n; ++p)\n                s += B",
+     "for (int p = j + 1; p < n; ++p)\n                s += B"),
+    ("trmm_no_alpha", "B[(size_t)i + (size_t)j * (size_t)ldb] = alpha * s;",
+     "B[(size_t)i + (size_t)j * (size_t)ldb] = s;"),
+    ("syrk_writes_upper", "for (int i = j; i < n; ++i) {\n            double *c =",
+     "for (int i = 0; i < n; ++i) {\n            double *c ="),
+    ("syrk_transposed_factor", "acc += A[(size_t)i + (size_t)p * (size_t)lda] * A[(size_t)j + (size_t)p * (size_t)lda];",
+     "acc += A[(size_t)i + (size_t)p * (size_t)lda] * A[(size_t)p + (size_t)j * (size_t)lda];"),
+    ("riccati_wrong_factor_block", "Lc = Fn + (size_t)nu + (size_t)nu * (size_t)ldf;", "Lc = Fn;"),
+    ("riccati_no_syrk", "oracle_dsyrk_ln(m, nx, 1.0, C, m, 1.0, Fn, ldf);", ""),
+    ("riccati_forward_order", "for (int n = N - 1; n >= 0; --n) {", "for (int n = 0; n < N; ++n) {"),
+    ("riccati_no_trmm", "oracle_dtrmm_rlnn(m, nx, 1.0, Lc, ldlc, C, m);", ""),
+    ("riccati_unreached_zero", "        info[n] = -1;\n    for (int j", "        info[n] = 0;\n    for (int j"),
+    ("riccati_continues_after_failure", "        if (info[n] != 0)\n            break;\n", ""),
 ]
 
 
