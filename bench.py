@@ -463,6 +463,117 @@ def backward_workload(torch, _lib, inputs, reps):
     return out
 
 
+def riccati_flops(nx, nu, N):
+    """Flops of one recursion by the paper's counting (App. D, Table 3: dsyrk
+    n^3, dpotrf n^3/3 for n x n operands; dtrmm of an m x n by an n x n
+    triangle m n^2): per stage m nx^2 + m^2 nx + m^3/3, plus nx^3/3."""
+    m = nu + nx
+    return N * (m * nx * nx + m * m * nx + m ** 3 / 3.0) + nx ** 3 / 3.0
+
+
+def riccati_bytes(nx, nu, N):
+    """Algorithmic HBM bytes of one recursion: BAt_n read, lower triangles of
+    RSQ_n and Q_N read, lower triangles of F_n and LN written, once each."""
+    m = nu + nx
+    tri_m, tri_x = m * (m + 1) // 2, nx * (nx + 1) // 2
+    return 8.0 * (N * (m * nx + 2 * tri_m) + 2 * tri_x)
+
+
+# Table 2 of the paper, BLASFEO API from C on one Haswell core at 3.4 GHz:
+# seconds per recursion (N = 10) -- context only, another machine and one
+# problem at a time.
+PAPER_RICCATI_S = {(8, 4): 3.24e-6, (24, 12): 2.29e-5, (40, 20): 7.95e-5, (64, 32): 2.87e-4}
+
+
+def riccati_workload(torch, _lib, inputs, reps, composed=True):
+    """The Riccati recursion of Sec. 5.2 at the paper's four (nx, nu), N = 10,
+    batched over independent problems: the fused one-wave-per-problem kernel,
+    and (composed) the same recursion as 3 N + 1 batched library calls --
+    dgemm NN for the dtrmm (the factor's upper triangle is zero), dgemm NT
+    with beta = 1 for the dsyrk, dpotrf -- in place on copies of the inputs."""
+    from paper_1902_08115_amd import blas
+    out = {}
+    N = inputs.RICCATI_N
+    stream = torch.cuda.current_stream()
+    for (nx, nu) in inputs.RICCATI_SHAPES:
+        m = nx + nu
+        batch = inputs.RICCATI_BATCH[(nx, nu)]
+        BAt, RSQ, QN = inputs.torch_riccati(nx, nu, N, batch, inputs.seed_for(42, nx))
+        F = torch.zeros((batch, N, m, m), dtype=torch.float64, device="cuda").transpose(2, 3)
+        LN = torch.zeros((batch, nx, nx), dtype=torch.float64, device="cuda").transpose(1, 2)
+        info = torch.empty((batch, N + 1), dtype=torch.int32, device="cuda")
+        work = blas.riccati_workspace(nx, nu, batch)
+
+        def fused():
+            blas.riccati(BAt, RSQ, QN, nu, F=F, LN=LN, info=info, work=work, stream=stream)
+
+        fused()
+        torch.cuda.synchronize()
+        assert int((info != 0).sum()) == 0, "Riccati factorization failed on SPD inputs"
+        best, med = time_events(torch, fused, reps)
+        fl, by = riccati_flops(nx, nu, N) * batch, riccati_bytes(nx, nu, N) * batch
+        rec = {"batch": batch, "N": N, "ms": round(best, 4), "median_ms": round(med, 4),
+               "recursions_per_s": round(batch / best * 1e3, 1),
+               "us_per_recursion_amortized": round(best * 1e3 / batch, 5),
+               "gflops": round(fl / best / 1e6, 1), "gbps": round(by / best / 1e6, 1),
+               "flops_per_recursion": riccati_flops(nx, nu, N),
+               "bytes_per_recursion": riccati_bytes(nx, nu, N),
+               "paper_blasfeo_api_c_haswell_s_per_recursion": PAPER_RICCATI_S[(nx, nu)]}
+        log(f"riccati nx={nx} nu={nu} N={N} batch={batch}: fused {best:.3f} ms "
+            f"({rec['gflops']} GFLOP/s, {rec['gbps']} GB/s)")
+        if composed:
+            Fc = RSQ.clone()
+            Lc = QN.clone()
+            infc = torch.empty((batch,), dtype=torch.int32, device="cuda")
+            C = torch.empty((batch, nx, m), dtype=torch.float64, device="cuda").transpose(1, 2)
+            s = stream.cuda_stream
+            ldf, stf, sf = m, m * m, N * m * m
+            ldb, stb, sb = m, m * nx, N * m * nx
+
+            def reset():
+                Fc.copy_(RSQ)
+                Lc.copy_(QN)
+                # zero strict upper triangles, which the composed dgemm reads
+                Fc.copy_(torch.tril(Fc))
+                Lc.copy_(torch.tril(Lc))
+
+            def comp():
+                st = _lib.dpotrf_strided_batched("L", nx, Lc.data_ptr(), nx, nx * nx,
+                                                 infc.data_ptr(), batch, s)
+                assert st == 0
+                prev, ldp, sp = Lc.data_ptr(), nx, nx * nx
+                for n in range(N - 1, -1, -1):
+                    fb = Fc.data_ptr() + 8 * n * stf
+                    st = _lib.dgemm_strided_batched("N", "N", m, nx, nx, 1.0,
+                                                    BAt.data_ptr() + 8 * n * stb, ldb, sb,
+                                                    prev, ldp, sp, 0.0, C.data_ptr(), m, m * nx,
+                                                    batch, s)
+                    assert st == 0
+                    st = _lib.dgemm_strided_batched("N", "T", m, m, nx, 1.0, C.data_ptr(), m,
+                                                    m * nx, C.data_ptr(), m, m * nx, 1.0, fb,
+                                                    ldf, sf, batch, s)
+                    assert st == 0
+                    st = _lib.dpotrf_strided_batched("L", m, fb, ldf, sf, infc.data_ptr(), batch, s)
+                    assert st == 0
+                    prev, ldp, sp = fb + 8 * (nu + nu * ldf), ldf, sf
+
+            reset()
+            comp()
+            torch.cuda.synchronize()
+            d = float((torch.tril(Fc) - torch.tril(F)).abs().max() / torch.tril(F).abs().max())
+            cbest, cmed = time_events(torch, comp, reps, reset)
+            rec["composed"] = {"ms": round(cbest, 4), "median_ms": round(cmed, 4),
+                               "launches": 3 * N + 1, "speedup_fused": round(cbest / best, 2),
+                               "max_rel_diff_vs_fused": d}
+            log(f"  composed 3N+1 launches: {cbest:.3f} ms (fused x{cbest / best:.2f}), "
+                f"diff {d:.1e}")
+            del Fc, Lc, C
+        out[f"nx{nx}_nu{nu}"] = rec
+        del BAt, RSQ, QN, F, LN, work
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -485,6 +596,8 @@ def main():
                     help="also measure the thin / flat / small dgemm sweeps")
     ap.add_argument("--uneven-modes", type=str, default="fused_graph,fused,grouped_graph,grouped",
                     help="plan execution modes timed on the uneven batch")
+    ap.add_argument("--riccati-only", action="store_true",
+                    help="only the Riccati recursion workload (profiling)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -514,10 +627,15 @@ def main():
     if args.crossover:
         crossover(torch, _lib, inputs, args)
         return
+    if args.riccati_only:
+        print(json.dumps({"next": {"riccati": riccati_workload(torch, _lib, inputs, args.steps)}}),
+              flush=True)
+        return
     if args.next_only:
         nxt = {"uneven_batch": uneven_batch(torch, _lib, inputs, args.steps,
                                             args.uneven_modes.split(","))}
         nxt["backward"] = backward_workload(torch, _lib, inputs, args.steps)
+        nxt["riccati"] = riccati_workload(torch, _lib, inputs, args.steps)
         if args.skinny:
             nxt["skinny"] = skinny_sweeps(torch, _lib, inputs, args.steps)
         print(json.dumps({"next": nxt}), flush=True)
@@ -632,6 +750,8 @@ def main():
         nxt = {"uneven_batch": uneven_batch(torch, _lib, inputs, 5, args.uneven_modes.split(","))}
         log("differentiation workload")
         nxt["backward"] = backward_workload(torch, _lib, inputs, 5)
+        log("Riccati recursion workload")
+        nxt["riccati"] = riccati_workload(torch, _lib, inputs, 5)
         if args.skinny:
             log("thin / flat / small dgemm sweeps")
             nxt["skinny"] = skinny_sweeps(torch, _lib, inputs, 5)

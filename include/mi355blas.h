@@ -12,6 +12,8 @@
  *     variant 'D' in Sec. 2.2; the four trans cases of App. D, Table 3).
  *   - dpotrf 'L': Sec. 3.1.5 (lower Cholesky factor A = L*L^T, L overwriting
  *     the lower triangle).
+ *   - the backward Riccati recursion of Sec. 5.2 (dtrmm_rlnn, dsyrk_ln and
+ *     dpotrf_l per stage), batched over independent problems.
  * The size switch between a direct (no staging) kernel for tiny operands and
  * an LDS-staged, packed kernel above a measured crossover follows the
  * variant-switching scheme of Sec. 2.4 and Sec. 3.1.
@@ -367,6 +369,65 @@ int mb_plan_stats(const mb_plan *plan, int64_t *out, int n);
 
 /* Wait for the plan's device, then free everything it owns.  NULL is a no-op. */
 int mb_plan_destroy(mb_plan *plan);
+
+/* ------------------------------------------------------ Riccati recursion --- */
+
+/*
+ * Batched backward Riccati recursion in the factorized form of Sec. 5.2,
+ * for independent problems with nx states, nu controls and horizon N
+ * (m = nu + nx):
+ *   LN   = chol(Q_N)                                         (lower)
+ *   for n = N-1 down to 0:
+ *     C_n  = BAt_n * Lc_{n+1}                (dtrmm_rlnn; Lc_N = LN)
+ *     F_n  = chol(RSQ_n + C_n * C_n^T) = [Lambda_n 0; L_n Lc_n]
+ *                                            (dsyrk_ln fused with dpotrf_l)
+ *     Lc_n = F_n(nu:m, nu:m), the lower Cholesky factor of P_n
+ * BAt_n = [B_n^T; A_n^T] is m x nx, RSQ_n = [R_n S_n; S_n^T Q_n] is m x m
+ * symmetric (lower triangle read), Q_N is nx x nx (lower triangle read).  With
+ * P = Lc_{n+1} Lc_{n+1}^T this is the Riccati update
+ *   P_n = Q + A^T P A - (S^T + A^T P B)(R + B^T P B)^{-1}(S + B^T P A).
+ * Layout: stage n of problem b of X starts at X + b*strideX + n*stageX,
+ * column-major with leading dimension ldX.  Input stage strides may be 0
+ * (time-invariant stages); inputs may be shared between problems.
+ * Outputs: the lower triangles of F_n (m x m) and LN (nx x nx); their strictly
+ * upper parts are never touched.  info (device, batch * (N+1) ints): entry
+ * b*(N+1) + n is the dpotrf info of stage n of problem b, entry b*(N+1) + N
+ * that of Q_N (LAPACK: 0, or the failing column + 1); a failed factorization
+ * stops that problem's recursion, and the stages below it are not computed
+ * (F untouched, info -1).  At a failing factorization only the columns before
+ * the failing one hold factor values; the rest of that output is unspecified.
+ * F may be RSQ itself (same pointer, ldf, stage and problem strides: in
+ * place), and LN may be QN itself; otherwise outputs must not overlap inputs,
+ * each other or the workspace.
+ * work: device workspace of work_bytes bytes, private to the call while it
+ * runs (calls that share one race).  Each wave of the kernel owns one slot of
+ * 2 KiB * ceil(m/16) * ceil(nx/16) and takes problems w, w + W, ...; W is the
+ * smallest of batch, the slots that fit in work_bytes and the waves the
+ * device holds at once.  mb_riccati_workspace_size gives the size for the
+ * largest W (one slot is enough for a correct, slower run).  m <= 304
+ * (MB_ERR_UNSUPPORTED above).
+ * Arguments: nx 1, nu 2, N 3, BAt 4, ldbat (>= max(1,m)) 5, stageBAt 6,
+ * strideBAt 7, RSQ 8, ldrsq (>= max(1,m)) 9, stageRSQ 10, strideRSQ 11, QN 12,
+ * ldq (>= max(1,nx)) 13, strideQ 14, F 15, ldf (>= max(1,m)) 16, stageF
+ * (>= ldf*(m-1)+m when N > 1) 17, strideF (>= (N-1)*stageF + ldf*(m-1)+m
+ * when batch > 1) 18, LN 19, ldl (>= max(1,nx)) 20, strideL
+ * (>= ldl*(nx-1)+nx when batch > 1) 21, info 22, work 23, work_bytes (at
+ * least one slot) 24, batch 25, stream 26.
+ */
+int mb_riccati_strided_batched(int nx, int nu, int N, const double *BAt, int ldbat,
+                               int64_t stageBAt, int64_t strideBAt, const double *RSQ, int ldrsq,
+                               int64_t stageRSQ, int64_t strideRSQ, const double *QN, int ldq,
+                               int64_t strideQ, double *F, int ldf, int64_t stageF,
+                               int64_t strideF, double *LN, int ldl, int64_t strideL, int *info,
+                               void *work, size_t work_bytes, int batch, hipStream_t stream);
+
+/*
+ * Workspace bytes for mb_riccati_strided_batched at full occupancy of the
+ * current device: one slot per wave the device holds at once, at most batch
+ * (at least one) slots.  Arguments: nx 1, nu 2, batch 3, bytes (host) 4;
+ * MB_ERR_UNSUPPORTED when nx + nu > 304, MB_ERR_HIP on a failed device query.
+ */
+int mb_riccati_workspace_size(int nx, int nu, int batch, size_t *bytes);
 
 /* ---------------------------------------------------------------- misc --- */
 

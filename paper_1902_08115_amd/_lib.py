@@ -33,6 +33,7 @@ EXPORTS = (
     "mb_dpotrf_l_backward_batched", "mb_dlaset_strided_batched", "mb_dlaset_batched",
     "mb_plan_create", "mb_plan_create_ex", "mb_plan_execute", "mb_plan_execute_mode", "mb_plan_stats",
     "mb_plan_destroy",
+    "mb_riccati_strided_batched", "mb_riccati_workspace_size",
     "mb_status_string", "mb_version",
 )
 
@@ -115,6 +116,10 @@ def _load():
     lib.mb_plan_execute_mode.argtypes = [vp, c_int, vp]
     lib.mb_plan_stats.argtypes = [vp, ctypes.POINTER(c_i64), c_int]
     lib.mb_plan_destroy.argtypes = [vp]
+    lib.mb_riccati_strided_batched.argtypes = [
+        c_int, c_int, c_int, vp, c_int, c_i64, c_i64, vp, c_int, c_i64, c_i64, vp, c_int, c_i64,
+        vp, c_int, c_i64, c_i64, vp, c_int, c_i64, vp, vp, ctypes.c_size_t, c_int, vp]
+    lib.mb_riccati_workspace_size.argtypes = [c_int, c_int, c_int, ctypes.POINTER(ctypes.c_size_t)]
     for name in EXPORTS:
         getattr(lib, name).restype = ctypes.c_char_p if name in _STRING_FNS else c_int
     return lib
@@ -226,6 +231,21 @@ def dlaset_strided_batched(uplo, m, n, alpha, beta, A, lda, sA, batch, stream=0)
 def dlaset_batched(uplo, m, n, alpha, beta, Aarr, lda, batch, stream=0) -> int:
     return lib.mb_dlaset_batched(_ch(uplo), m, n, float(alpha), float(beta), Aarr, lda, batch,
                                  stream)
+
+
+def riccati_strided_batched(nx, nu, N, BAt, ldbat, stBAt, sBAt, RSQ, ldrsq, stRSQ, sRSQ, QN, ldq,
+                            sQ, F, ldf, stF, sF, LN, ldl, sL, info, work, work_bytes, batch,
+                            stream=0) -> int:
+    return lib.mb_riccati_strided_batched(nx, nu, N, BAt, ldbat, stBAt, sBAt, RSQ, ldrsq, stRSQ,
+                                          sRSQ, QN, ldq, sQ, F, ldf, stF, sF, LN, ldl, sL, info,
+                                          work, work_bytes, batch, stream)
+
+
+def riccati_workspace_size(nx, nu, batch):
+    """(status, bytes) of mb_riccati_workspace_size."""
+    out = ctypes.c_size_t(0)
+    st = lib.mb_riccati_workspace_size(nx, nu, batch, ctypes.byref(out))
+    return st, out.value
 
 
 def version() -> int:

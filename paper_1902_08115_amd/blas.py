@@ -138,6 +138,63 @@ def dpotrf_batched(Aptr, n, lda, batch, info=None, stream=None):
     return info
 
 
+def _stages(X: torch.Tensor, name: str, rows: int, cols: int):
+    """(ld, stage stride, problem stride) of a (batch, N, rows, cols) tensor of
+    column-major FP64 matrices."""
+    if X.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not X.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if X.dim() != 4 or tuple(X.shape[2:]) != (rows, cols):
+        raise ValueError(f"{name} must be (batch, N, {rows}, {cols})")
+    if rows > 1 and X.stride(2) != 1:
+        raise ValueError(f"{name} is not column-major (stride(2) must be 1)")
+    ld = X.stride(3) if cols > 1 else max(1, rows, X.stride(3))
+    return ld, X.stride(1), X.stride(0)
+
+
+def riccati_workspace(nx, nu, batch, device="cuda"):
+    """A workspace tensor sized by mb_riccati_workspace_size (full occupancy)."""
+    st, nbytes = _lib.riccati_workspace_size(nx, nu, batch)
+    _raise("mb_riccati_workspace_size", st)
+    return torch.empty(max(1, (nbytes + 7) // 8), dtype=torch.float64, device=device)
+
+
+def riccati(BAt, RSQ, QN, nu, F=None, LN=None, info=None, work=None, stream=None):
+    """Batched factorized Riccati recursion (Sec. 5.2).
+
+    BAt (batch, N, m, nx), RSQ (batch, N, m, m), QN (batch, nx, nx): column-
+    major FP64 GPU tensors, m = nu + nx.  F (batch, N, m, m), LN
+    (batch, nx, nx) and info (batch, N + 1) int32 are written (allocated when
+    None; F and LN zero-filled then, so their upper triangles read zero);
+    ``work`` is a device tensor used as the workspace (allocated when None).
+    Returns (F, LN, info)."""
+    batch, N, m, nx = BAt.shape
+    if m != nu + nx:
+        raise ValueError("BAt rows must be nu + nx")
+    if F is None:
+        F = torch.zeros((batch, N, m, m), dtype=torch.float64, device=BAt.device).transpose(2, 3)
+    if LN is None:
+        LN = torch.zeros((batch, nx, nx), dtype=torch.float64, device=BAt.device).transpose(1, 2)
+    if info is None:
+        info = torch.empty((batch, N + 1), dtype=torch.int32, device=BAt.device)
+    if work is None:
+        work = riccati_workspace(nx, nu, batch, device=BAt.device)
+    ldb, stb, sb = _stages(BAt, "BAt", m, nx)
+    ldr, str_, sr = _stages(RSQ, "RSQ", m, m)
+    ldf, stf, sf = _stages(F, "F", m, m)
+    ldq, sq = _layout(QN, "QN", True)
+    ldl, sl = _layout(LN, "LN", True)
+    if info.dtype != torch.int32 or not info.is_contiguous() or info.numel() != batch * (N + 1):
+        raise ValueError("info must be a contiguous int32 tensor of batch * (N + 1) entries")
+    st = _lib.riccati_strided_batched(
+        nx, nu, N, BAt.data_ptr(), ldb, stb, sb, RSQ.data_ptr(), ldr, str_, sr, QN.data_ptr(), ldq,
+        sq, F.data_ptr(), ldf, stf, sf, LN.data_ptr(), ldl, sl, info.data_ptr(), work.data_ptr(),
+        work.numel() * work.element_size(), batch, _stream(stream))
+    _raise("mb_riccati_strided_batched", st)
+    return F, LN, info
+
+
 class Plan:
     """An uneven batch of dgemm / dpotrf problems run by one persistent kernel.
 

@@ -69,6 +69,30 @@ struct LasetArgs {
     int batch;
 };
 
+// One batched Riccati recursion call, already validated.  Problem b, stage n
+// of X is at X + b * sX + n * stX; info has N + 1 entries per problem.
+struct RiccatiArgs {
+    int nx, nu, N;
+    const double *BAt;
+    int64_t stBAt, sBAt;
+    int ldbat;
+    const double *RSQ;
+    int64_t stRSQ, sRSQ;
+    int ldrsq;
+    const double *QN;
+    int64_t sQ;
+    int ldq;
+    double *F;
+    int64_t stF, sF;
+    int ldf;
+    double *LN;
+    int64_t sL;
+    int ldl;
+    int *info;
+    double *work;  // riccati_slot_doubles(nx, nu) doubles per wave
+    int64_t batch;
+};
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // Pointers known to address global memory.  Addresses that reach a kernel
@@ -192,6 +216,9 @@ int packed_config_wave_limit(int config);  // > 0: largest m, n of a WAVE shape;
 hipError_t launch_fused(const FusedArgs &a, int grid, hipStream_t s);
 hipError_t fused_grid(int *grid, int *waves_per_cu);  // persistent grid for the current device
 hipError_t launch_scatter_info(const int *src, int *const *dst, int count, hipStream_t s);
+int64_t riccati_slot_doubles(int nx, int nu);  // workspace of one wave
+hipError_t riccati_max_waves(int *waves);      // waves resident at once on the device
+hipError_t launch_riccati(const RiccatiArgs &a, int waves, hipStream_t s);
 
 // Validated dgemm / dpotrf launches used by the C ABI and by plans (api.hip):
 // quick returns, size-class dispatch, launch.  Return an MB_ status.

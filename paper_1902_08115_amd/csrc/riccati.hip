@@ -1,0 +1,229 @@
+// riccati.hip -- batched backward Riccati recursion in the factorized form of
+// Sec. 5.2: for each independent problem, Lc_N = chol(Q_N), then for
+// n = N-1 .. 0
+//   C_n = [B_n^T; A_n^T] * Lc_{n+1}                 (dtrmm_rlnn)
+//   F_n = chol([R_n S_n; S_n^T Q_n] + C_n C_n^T)    (dsyrk_ln + dpotrf_l)
+//   Lc_n = bottom-right nx x nx block of F_n.
+//
+// One wave runs one problem's whole recursion, so the stages -- which depend
+// on each other -- never leave the wave, and the batch supplies the
+// parallelism.  The paper credits part of its API's advantage on this
+// workload to a routine that fuses dsyrk with the following dpotrf
+// (Sec. 5.2); here the fusion is complete: the C_n C_n^T terms are added into
+// the same accumulators as the left-looking Cholesky update, so the matrix
+// R + C C^T is never written out.  Per stage:
+//   1. dtrmm: every 16 x 16 tile of C_n is a sum of MFMA tile products of
+//      BAt_n and the lower factor of the previous stage (read transposed
+//      through the cache; its upper triangle is masked, never read); the tile
+//      goes to the wave's workspace slot in a lane-private order (one
+//      coalesced 512-byte row per register), since C_n is needed in full
+//      while the factor is formed;
+//   2. fused dsyrk + dpotrf by block column J: tile (I,J) of RSQ_n plus
+//      sum_K C(I,K) C(J,K)^T minus sum_{K<J} F(I,K) F(J,K)^T, then the
+//      diagonal tile factored in registers (factor_diag_tile) and the panel
+//      solved against its inverse -- the structure of potrf_wave.h, with the
+//      syrk terms in the same accumulation.
+// The grid is a fixed set of waves (at most what the device holds at once),
+// each owning one workspace slot and taking problems b = w, w + W, ... in
+// turn; all problems have the same shape, so the static split is balanced,
+// and a slot is rewritten problem after problem while it is still cached.
+#include <limits.h>
+
+#include "potrf_wave.h"
+
+namespace mb {
+
+constexpr int RIC_WPB = 4;  // waves (independent workers) per workgroup
+
+__device__ __forceinline__ void ric_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// acc + X * Y^T for tiles in accumulator order.
+__device__ __forceinline__ d4 add_xyT(d4 acc, const d4 &x, const d4 &y)
+{
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        acc = mfma16(y[s], x[s], acc);
+    return acc;
+}
+
+// Tile (I, T) of the rows x cols matrix X, zero outside it.
+__device__ __forceinline__ d4 load_rect(const MB_GLOBAL double *X, size_t ld, int rows, int cols,
+                                        int I, int T, int lr, int lg)
+{
+    d4 t;
+    const int gi = 16 * I + lr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int gc = 16 * T + lg + 4 * r;
+        t[r] = (gi < rows && gc < cols) ? X[(size_t)gi + (size_t)gc * ld] : 0.0;
+    }
+    return t;
+}
+
+// Y with Y[i][c] = L(16T + c, 16K + i) for the nx x nx lower factor L (its
+// strictly upper part reads as zero, outside the matrix zero): the transpose
+// of tile (T, K), so that X * Y^T multiplies by L(T, K).
+__device__ __forceinline__ d4 load_lower_t(const MB_GLOBAL double *L, size_t ld, int nx, int T, int K,
+                                           int lr, int lg)
+{
+    d4 t;
+    const int col = 16 * K + lr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * T + lg + 4 * r;
+        t[r] = (row < nx && col < nx && row >= col) ? L[(size_t)row + (size_t)col * ld] : 0.0;
+    }
+    return t;
+}
+
+// Workspace tile (I, K) of C: register r of lane l at tile * 256 + r * 64 + l.
+__device__ __forceinline__ d4 ws_load(const MB_GLOBAL double *W, int ntk, int I, int K, int lane)
+{
+    const MB_GLOBAL double *p = W + ((size_t)I * ntk + K) * 256 + lane;
+    return d4{p[0], p[64], p[128], p[192]};
+}
+__device__ __forceinline__ void ws_store(MB_GLOBAL double *W, int ntk, int I, int K, const d4 &t,
+                                         int lane)
+{
+    MB_GLOBAL double *p = W + ((size_t)I * ntk + K) * 256 + lane;
+    p[0] = t[0];
+    p[64] = t[1];
+    p[128] = t[2];
+    p[192] = t[3];
+}
+
+// C = BAt * L into the workspace: BAt is m x nx, L the nx x nx lower factor;
+// ntm = ceil(m / 16) by ntx = ceil(nx / 16) tiles, zero outside m x nx.
+__device__ __forceinline__ void trmm_wave(const MB_GLOBAL double *BAt, size_t ldb, const MB_GLOBAL double *L,
+                                          size_t ldl, int m, int nx, int ntm, int ntx,
+                                          MB_GLOBAL double *W, int lane)
+{
+    const int lr = lane & 15, lg = lane >> 4;
+    for (int I = 0; I < ntm; ++I)
+        for (int K = 0; K < ntx; ++K) {
+            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+            for (int T = K; T < ntx; ++T) {
+                const d4 x = load_rect(BAt, ldb, m, nx, I, T, lr, lg);
+                const d4 y = load_lower_t(L, ldl, nx, T, K, lr, lg);
+                acc = add_xyT(acc, x, y);
+            }
+            ws_store(W, ntx, I, K, acc, lane);
+        }
+    ric_fence();
+}
+
+// F = chol(S + C C^T) for the m x m symmetric S (lower triangle read) and the
+// ntk tile columns of C in the workspace (ntk = 0: F = chol(S)).  Only the
+// lower triangle of F is written, and at a failing pivot only the columns
+// before it.  Returns the LAPACK info (0, or the failing column + 1).
+__device__ __forceinline__ int syrk_potrf_wave(const MB_GLOBAL double *Sm, size_t lds, MB_GLOBAL double *F,
+                                               size_t ldf, int m, int nt, const MB_GLOBAL double *W,
+                                               int ntk, PotrfSmem &S, int lane)
+{
+    const int lr = lane & 15, lg = lane >> 4;
+    if (lane == 0)
+        S.fail = INT_MAX;
+    wave_lds_sync();
+    for (int J = 0; J < nt; ++J) {
+        d4 t = load_tile(Sm, lds, m, J, J, lr, lg, true);
+        for (int K = 0; K < ntk; ++K) {
+            const d4 c = ws_load(W, ntk, J, K, lane);
+            t = add_xyT(t, c, c);
+        }
+        for (int K = 0; K < J; ++K) {
+            const d4 l = load_tile(F, ldf, m, J, K, lr, lg, false);
+            t = update_nt(t, l, l);
+        }
+        d4 w;
+        factor_diag_tile(t, w, S, J, lane);
+        wave_lds_sync();
+        const int fail_col = S.fail;
+        store_diag(F, ldf, m, J, t, fail_col, lr, lg);
+        for (int I = J + 1; I < nt; ++I) {
+            d4 a = load_tile(Sm, lds, m, I, J, lr, lg, false);
+            for (int K = 0; K < ntk; ++K)
+                a = add_xyT(a, ws_load(W, ntk, I, K, lane), ws_load(W, ntk, J, K, lane));
+            for (int K = 0; K < J; ++K)
+                a = update_nt(a, load_tile(F, ldf, m, I, K, lr, lg, false),
+                              load_tile(F, ldf, m, J, K, lr, lg, false));
+            store_tile(F, ldf, m, I, J, solve_right(a, w), fail_col, lr, lg);
+        }
+        // later block columns, and the next stage, read these tiles back
+        ric_fence();
+        if (fail_col != INT_MAX)
+            break;
+    }
+    return (S.fail == INT_MAX) ? 0 : S.fail + 1;
+}
+
+__global__ __launch_bounds__(RIC_WPB * 64) void riccati_kernel(RiccatiArgs p, int waves)
+{
+    __shared__ PotrfSmem smem[RIC_WPB];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int w = blockIdx.x * RIC_WPB + wave;
+    if (w >= waves)
+        return;
+    PotrfSmem &S = smem[wave];
+    const int nx = p.nx, nu = p.nu, N = p.N, m = nx + nu;
+    const int ntm = (m + 15) / 16, ntx = (nx + 15) / 16;
+    MB_GLOBAL double *W = global_ptr(p.work) + (size_t)w * ((size_t)ntm * ntx * 256);
+    for (int64_t b = w; b < p.batch; b += waves) {
+        MB_GLOBAL int *info = global_ptr(p.info) + b * (N + 1);
+        const MB_GLOBAL double *QN = global_ptr(p.QN) + b * p.sQ;
+        MB_GLOBAL double *LN = global_ptr(p.LN) + b * p.sL;
+        int st = syrk_potrf_wave(QN, (size_t)p.ldq, LN, (size_t)p.ldl, nx, ntx, W, 0, S, lane);
+        if (lane == 0)
+            info[N] = st;
+        int n = N - 1;
+        const MB_GLOBAL double *Lc = LN;
+        size_t ldlc = (size_t)p.ldl;
+        for (; st == 0 && n >= 0; --n) {
+            const MB_GLOBAL double *BAt = global_ptr(p.BAt) + b * p.sBAt + n * p.stBAt;
+            const MB_GLOBAL double *RSQ = global_ptr(p.RSQ) + b * p.sRSQ + n * p.stRSQ;
+            MB_GLOBAL double *F = global_ptr(p.F) + b * p.sF + n * p.stF;
+            trmm_wave(BAt, (size_t)p.ldbat, Lc, ldlc, m, nx, ntm, ntx, W, lane);
+            st = syrk_potrf_wave(RSQ, (size_t)p.ldrsq, F, (size_t)p.ldf, m, ntm, W, ntx, S, lane);
+            if (lane == 0)
+                info[n] = st;
+            Lc = F + (size_t)nu + (size_t)nu * (size_t)p.ldf;
+            ldlc = (size_t)p.ldf;
+        }
+        // stages below a failure are not computed
+        for (int q = lane; q <= n; q += 64)
+            info[q] = -1;
+    }
+}
+
+int64_t riccati_slot_doubles(int nx, int nu)
+{
+    const int64_t ntm = (nx + nu + 15) / 16, ntx = (nx + 15) / 16;
+    return ntm * ntx * 256;
+}
+
+hipError_t riccati_max_waves(int *waves)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, riccati_kernel, RIC_WPB * 64, 0);
+    if (e != hipSuccess)
+        return e;
+    *waves = std::max(1, cus * std::max(per_cu, 1) * RIC_WPB);
+    return hipSuccess;
+}
+
+hipError_t launch_riccati(const RiccatiArgs &a, int waves, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((waves + RIC_WPB - 1) / RIC_WPB);
+    hipLaunchKernelGGL(riccati_kernel, dim3(blocks), dim3(RIC_WPB * 64), 0, s, a, waves);
+    return hipGetLastError();
+}
+
+}  // namespace mb

@@ -268,3 +268,52 @@ def torch_symmetric(batch: int, n: int, seed: int, device="cuda"):
     X.uniform_(-1.0, 1.0, generator=gen)
     X = 0.5 * (X + X.transpose(1, 2))
     return X.contiguous().transpose(1, 2)
+
+
+# ----------------------------------------------------------------------------
+# Riccati recursion (Sec. 5.2): horizon N = 10, (nx, nu) of the paper's
+# Table 2.  The paper does not give its system matrices; the recipe below
+# draws well-conditioned ones: BAt_n = [B_n^T; A_n^T] uniform [-1, 1) / sqrt(nx)
+# (spectral radius of A about 1, so P_n neither explodes nor vanishes over the
+# horizon), RSQ_n = W W^T / m + I and Q_N = V V^T / nx + I with W, V uniform
+# [-1, 1) (symmetric positive definite, eigenvalues in [1, 1 + m/3]).
+# ----------------------------------------------------------------------------
+
+RICCATI_N = 10
+RICCATI_SHAPES = ((8, 4), (24, 12), (40, 20), (64, 32))
+# problems per batch: enough waves to fill the device several times over for
+# every shape, about 4-16 GB of operands per shape
+RICCATI_BATCH = {(8, 4): 131072, (24, 12): 32768, (40, 20): 16384, (64, 32): 8192}
+
+
+def torch_riccati(nx: int, nu: int, N: int, batch: int, seed: int, device="cuda",
+                  chunk: int = 1024):
+    """(BAt, RSQ, QN): column-major FP64 tensors of shapes (batch, N, m, nx),
+    (batch, N, m, m) and (batch, nx, nx), m = nu + nx, drawn by the recipe
+    above with one seeded generator (BAt first, then RSQ, then QN, in chunks
+    of `chunk` problems)."""
+    import torch
+    m = nu + nx
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    f64 = torch.float64
+    bat = torch.empty((batch, N, nx, m), dtype=f64, device=device)
+    rsq = torch.empty((batch, N, m, m), dtype=f64, device=device)
+    q = torch.empty((batch, nx, nx), dtype=f64, device=device)
+    eye_m = torch.eye(m, dtype=f64, device=device)
+    eye_x = torch.eye(nx, dtype=f64, device=device)
+    for b0 in range(0, batch, chunk):
+        b1 = min(batch, b0 + chunk)
+        bat[b0:b1].uniform_(-1.0, 1.0, generator=gen)
+        bat[b0:b1] *= 1.0 / math.sqrt(max(nx, 1))
+        W = torch.empty((b1 - b0, N, m, m), dtype=f64, device=device)
+        W.uniform_(-1.0, 1.0, generator=gen)
+        S = torch.matmul(W, W.transpose(2, 3).contiguous()) / max(m, 1)
+        rsq[b0:b1] = 0.5 * (S + S.transpose(2, 3)) + eye_m
+        V = torch.empty((b1 - b0, nx, nx), dtype=f64, device=device)
+        V.uniform_(-1.0, 1.0, generator=gen)
+        T = torch.matmul(V, V.transpose(1, 2).contiguous()) / max(nx, 1)
+        q[b0:b1] = 0.5 * (T + T.transpose(1, 2)) + eye_x
+    # RSQ and QN are symmetric: their row-major buffers are the column-major ones
+    return bat.transpose(2, 3), rsq.transpose(2, 3), q.transpose(1, 2)
+

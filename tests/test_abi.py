@@ -266,3 +266,41 @@ def test_variant_range_and_skinny_dispatch(L):
     assert L.dgemm_kernel_name("N", "N", 4, 300, 300, L.VARIANT_REGTILE) == "gemm_regtile_t12"
     assert L.dgemm_kernel_name("N", "N", 300, 4, 300, L.VARIANT_REGTILE) == "gemm_regtile_t21"
     assert L.dgemm_select("N", "N", 4, 300, 300) in (1, 2, 3)
+
+
+def test_riccati_argument_errors(L):
+    """Each illegal argument of mb_riccati_strided_batched returns its
+    position before anything is queried or launched; batch 0 returns MB_OK."""
+    nx, nu, N, b = 8, 4, 3, 2
+    m = nx + nu
+    sf = m * m
+    ok = dict(nx=nx, nu=nu, N=N, BAt=P, ldbat=m, stBAt=m * nx, sBAt=N * m * nx, RSQ=P, ldrsq=m,
+              stRSQ=sf, sRSQ=N * sf, QN=P, ldq=nx, sQ=nx * nx, F=P, ldf=m, stF=sf, sF=N * sf,
+              LN=P, ldl=nx, sL=nx * nx, info=P, work=P, work_bytes=1 << 20, batch=b, stream=None)
+    order = list(ok)
+
+    def call(**kw):
+        a = dict(ok)
+        a.update(kw)
+        return L.riccati_strided_batched(*[a[k] for k in order])
+
+    bad = [("nx", -1, -1), ("nu", -1, -2), ("N", -1, -3), ("ldbat", m - 1, -5), ("stBAt", -1, -6),
+           ("sBAt", -1, -7), ("ldrsq", m - 1, -9), ("stRSQ", -1, -10), ("sRSQ", -1, -11),
+           ("ldq", nx - 1, -13), ("sQ", -1, -14), ("ldf", m - 1, -16), ("stF", sf - 1, -17),
+           ("sF", N * sf - 1, -18), ("ldl", nx - 1, -20), ("sL", nx * nx - 1, -21),
+           ("batch", -1, -25), ("BAt", None, -4), ("RSQ", None, -8), ("QN", None, -12),
+           ("F", None, -15), ("LN", None, -19), ("info", None, -22), ("work", None, -23),
+           ("work_bytes", 2047, -24)]
+    for key, val, want in bad:
+        assert call(**{key: val}) == want, (key, val)
+    assert call(batch=0) == 0
+    assert call(nx=300, nu=5, ldbat=305, ldrsq=305, ldq=300, ldf=305, ldl=300, stF=305 * 305,
+                sF=N * 305 * 305, sL=300 * 300) == L.MB_ERR_UNSUPPORTED
+    # input strides may be 0 (time-invariant stages, shared inputs)
+    assert call(stBAt=0, sBAt=0, stRSQ=0, sRSQ=0, sQ=0, batch=0) == 0
+    st, _ = L.riccati_workspace_size(-1, 0, 1)
+    assert st == -1
+    assert L.riccati_workspace_size(4, -1, 1)[0] == -2
+    assert L.riccati_workspace_size(4, 1, -1)[0] == -3
+    assert L.lib.mb_riccati_workspace_size(4, 1, 1, None) == -4
+    assert L.riccati_workspace_size(300, 5, 1)[0] == L.MB_ERR_UNSUPPORTED
