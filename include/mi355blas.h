@@ -373,6 +373,33 @@ int mb_plan_destroy(mb_plan *plan);
 /* ------------------------------------------------------ Riccati recursion --- */
 
 /*
+ * Batched BLAS dtrmm with side 'R', uplo 'L', trans 'N', diag 'N' (Sec. 3.1.4;
+ * the dtrmm_rlnn of Sec. 5.2), in place:  B <= alpha * B * A  for each m x n
+ * B and n x n lower-triangular A (its strictly upper part is never read).
+ * alpha == 0 sets B to zero without reading A.  B must not overlap A.
+ * Arguments: m 1, n 2, alpha 3, A 4, lda (>= max(1,n)) 5, strideA 6, B 7,
+ * ldb (>= max(1,m)) 8, strideB (>= ldb*(n-1)+m when batch > 1) 9, batch 10,
+ * stream 11.
+ */
+int mb_dtrmm_rlnn_strided_batched(int m, int n, double alpha, const double *A, int lda,
+                                  int64_t strideA, double *B, int ldb, int64_t strideB, int batch,
+                                  hipStream_t stream);
+
+/*
+ * Batched BLAS dsyrk with uplo 'L', trans 'N' (Sec. 3.1.2; the dsyrk_ln of
+ * Sec. 5.2): the lower triangle of C <= alpha * A * A^T + beta * C for each
+ * n x n C and n x k A; the strictly upper triangle of C is never touched.
+ * BLAS scalar rules: beta == 0 does not read C; alpha == 0 or k == 0 does not
+ * read A; with beta == 1 as well the call returns at once.  C must not
+ * overlap A.  Arguments: n 1, k 2, alpha 3, A 4, lda (>= max(1,n)) 5,
+ * strideA 6, beta 7, C 8, ldc (>= max(1,n)) 9, strideC (>= ldc*(n-1)+n when
+ * batch > 1) 10, batch 11, stream 12.
+ */
+int mb_dsyrk_ln_strided_batched(int n, int k, double alpha, const double *A, int lda,
+                                int64_t strideA, double beta, double *C, int ldc, int64_t strideC,
+                                int batch, hipStream_t stream);
+
+/*
  * Batched backward Riccati recursion in the factorized form of Sec. 5.2,
  * for independent problems with nx states, nu controls and horizon N
  * (m = nu + nx):

@@ -33,6 +33,7 @@ EXPORTS = (
     "mb_dpotrf_l_backward_batched", "mb_dlaset_strided_batched", "mb_dlaset_batched",
     "mb_plan_create", "mb_plan_create_ex", "mb_plan_execute", "mb_plan_execute_mode", "mb_plan_stats",
     "mb_plan_destroy",
+    "mb_dtrmm_rlnn_strided_batched", "mb_dsyrk_ln_strided_batched",
     "mb_riccati_strided_batched", "mb_riccati_workspace_size",
     "mb_status_string", "mb_version",
 )
@@ -116,6 +117,10 @@ def _load():
     lib.mb_plan_execute_mode.argtypes = [vp, c_int, vp]
     lib.mb_plan_stats.argtypes = [vp, ctypes.POINTER(c_i64), c_int]
     lib.mb_plan_destroy.argtypes = [vp]
+    lib.mb_dtrmm_rlnn_strided_batched.argtypes = [c_int, c_int, c_double, vp, c_int, c_i64, vp,
+                                                  c_int, c_i64, c_int, vp]
+    lib.mb_dsyrk_ln_strided_batched.argtypes = [c_int, c_int, c_double, vp, c_int, c_i64, c_double,
+                                                vp, c_int, c_i64, c_int, vp]
     lib.mb_riccati_strided_batched.argtypes = [
         c_int, c_int, c_int, vp, c_int, c_i64, c_i64, vp, c_int, c_i64, c_i64, vp, c_int, c_i64,
         vp, c_int, c_i64, c_i64, vp, c_int, c_i64, vp, vp, ctypes.c_size_t, c_int, vp]
@@ -231,6 +236,16 @@ def dlaset_strided_batched(uplo, m, n, alpha, beta, A, lda, sA, batch, stream=0)
 def dlaset_batched(uplo, m, n, alpha, beta, Aarr, lda, batch, stream=0) -> int:
     return lib.mb_dlaset_batched(_ch(uplo), m, n, float(alpha), float(beta), Aarr, lda, batch,
                                  stream)
+
+
+def dtrmm_rlnn_strided_batched(m, n, alpha, A, lda, sA, B, ldb, sB, batch, stream=0) -> int:
+    return lib.mb_dtrmm_rlnn_strided_batched(m, n, float(alpha), A, lda, sA, B, ldb, sB, batch,
+                                             stream)
+
+
+def dsyrk_ln_strided_batched(n, k, alpha, A, lda, sA, beta, C, ldc, sC, batch, stream=0) -> int:
+    return lib.mb_dsyrk_ln_strided_batched(n, k, float(alpha), A, lda, sA, float(beta), C, ldc, sC,
+                                           batch, stream)
 
 
 def riccati_strided_batched(nx, nu, N, BAt, ldbat, stBAt, sBAt, RSQ, ldrsq, stRSQ, sRSQ, QN, ldq,

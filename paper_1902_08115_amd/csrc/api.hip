@@ -559,6 +559,53 @@ int mb_dlaset_batched(char uplo, int m, int n, double alpha, double beta, double
     return to_status(mb::launch_laset(a, stream));
 }
 
+int mb_dtrmm_rlnn_strided_batched(int m, int n, double alpha, const double *A, int lda,
+                                  int64_t strideA, double *B, int ldb, int64_t strideB, int batch,
+                                  hipStream_t stream)
+{
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (lda < std::max(1, n)) return -5;
+    if (strideA < 0) return -6;
+    if (ldb < std::max(1, m)) return -8;
+    if (strideB < 0 || (batch > 1 && m > 0 && n > 0 && strideB < (int64_t)ldb * (n - 1) + m))
+        return -9;
+    if (batch < 0) return -10;
+    if (m == 0 || n == 0 || batch == 0)
+        return MB_OK;
+    if (!A && alpha != 0.0) return -4;
+    if (!B) return -7;
+    mb::TrmmArgs a{};
+    a.m = m; a.n = n; a.alpha = alpha;
+    a.A = A; a.sA = strideA; a.lda = lda;
+    a.B = B; a.sB = strideB; a.ldb = ldb;
+    a.batch = batch;
+    return to_status(mb::launch_trmm_rlnn(a, stream));
+}
+
+int mb_dsyrk_ln_strided_batched(int n, int k, double alpha, const double *A, int lda,
+                                int64_t strideA, double beta, double *C, int ldc, int64_t strideC,
+                                int batch, hipStream_t stream)
+{
+    if (n < 0) return -1;
+    if (k < 0) return -2;
+    if (lda < std::max(1, n)) return -5;
+    if (strideA < 0) return -6;
+    if (ldc < std::max(1, n)) return -9;
+    if (strideC < 0 || (batch > 1 && n > 0 && strideC < (int64_t)ldc * (n - 1) + n)) return -10;
+    if (batch < 0) return -11;
+    if (n == 0 || batch == 0 || ((alpha == 0.0 || k == 0) && beta == 1.0))
+        return MB_OK;
+    if (!A && alpha != 0.0 && k > 0) return -4;
+    if (!C) return -8;
+    mb::SyrkArgs a{};
+    a.n = n; a.k = k; a.alpha = (k == 0) ? 0.0 : alpha; a.beta = beta;
+    a.A = A; a.sA = strideA; a.lda = lda;
+    a.C = C; a.sC = strideC; a.ldc = ldc;
+    a.batch = batch;
+    return to_status(mb::launch_syrk_ln(a, stream));
+}
+
 int mb_riccati_workspace_size(int nx, int nu, int batch, size_t *bytes)
 {
     if (nx < 0) return -1;

@@ -69,6 +69,32 @@ struct LasetArgs {
     int batch;
 };
 
+// One batched dtrmm ('R','L','N','N': B <= alpha B A) call, already validated.
+struct TrmmArgs {
+    int m, n;
+    double alpha;
+    const double *A;
+    int64_t sA;
+    int lda;
+    double *B;
+    int64_t sB;
+    int ldb;
+    int batch;
+};
+
+// One batched dsyrk ('L','N': lower C <= alpha A A^T + beta C) call, validated.
+struct SyrkArgs {
+    int n, k;
+    double alpha, beta;
+    const double *A;
+    int64_t sA;
+    int lda;
+    double *C;
+    int64_t sC;
+    int ldc;
+    int batch;
+};
+
 // One batched Riccati recursion call, already validated.  Problem b, stage n
 // of X is at X + b * sX + n * stX; info has N + 1 entries per problem.
 struct RiccatiArgs {
@@ -173,6 +199,17 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
 }
 
+// Make this wave's global stores visible to its own later global loads (from
+// any lane).  The lanes of a wave share one CU and its vector L1, which the
+// stores update on their way to L2, so a workgroup-scope release/acquire pair
+// suffices: it waits until the stores have completed and needs no cache
+// invalidation (an agent-scope acquire would also invalidate L2 lines).
+__device__ __forceinline__ void wave_mem_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 template <bool WAVE_ONLY>
 __device__ __forceinline__ void group_sync()
 {
@@ -216,6 +253,8 @@ int packed_config_wave_limit(int config);  // > 0: largest m, n of a WAVE shape;
 hipError_t launch_fused(const FusedArgs &a, int grid, hipStream_t s);
 hipError_t fused_grid(int *grid, int *waves_per_cu);  // persistent grid for the current device
 hipError_t launch_scatter_info(const int *src, int *const *dst, int count, hipStream_t s);
+hipError_t launch_trmm_rlnn(const TrmmArgs &a, hipStream_t s);
+hipError_t launch_syrk_ln(const SyrkArgs &a, hipStream_t s);
 int64_t riccati_slot_doubles(int nx, int nu);  // workspace of one wave
 hipError_t riccati_max_waves(int *waves);      // waves resident at once on the device
 hipError_t launch_riccati(const RiccatiArgs &a, int waves, hipStream_t s);

@@ -133,13 +133,8 @@ __device__ __forceinline__ d4 adj_transpose(const d4 &x, AdjSmem &S, int lane)
     return y;
 }
 
-// Make this wave's global stores visible to its own later loads (complete
-// them, drop stale L1 lines).
-__device__ __forceinline__ void adj_fence()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
+// Make this wave's global stores visible to its own later loads.
+__device__ __forceinline__ void adj_fence() { wave_mem_sync(); }
 
 // Abar <= adjoint of the Cholesky factorization at L for the cotangent Lbar
 // (lower triangles of L and Lbar are read; the whole n x n Abar is written).

@@ -289,10 +289,8 @@ __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT
         }
         if (fail_col != INT_MAX || J + STEP >= NT)
             break;
-        // the next steps read these block columns back: make the stores
-        // visible to this wave's later loads (complete them, drop stale L1)
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // the next steps read these block columns back
+        wave_mem_sync();
     }
     return (S.fail == INT_MAX) ? 0 : S.fail + 1;
 }

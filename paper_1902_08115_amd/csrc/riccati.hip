@@ -35,12 +35,6 @@ namespace mb {
 
 constexpr int RIC_WPB = 4;  // waves (independent workers) per workgroup
 
-__device__ __forceinline__ void ric_fence()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
 // acc + X * Y^T for tiles in accumulator order.
 __device__ __forceinline__ d4 add_xyT(d4 acc, const d4 &x, const d4 &y)
 {
@@ -113,7 +107,7 @@ __device__ __forceinline__ void trmm_wave(const MB_GLOBAL double *BAt, size_t ld
             }
             ws_store(W, ntx, I, K, acc, lane);
         }
-    ric_fence();
+    wave_mem_sync();
 }
 
 // F = chol(S + C C^T) for the m x m symmetric S (lower triangle read) and the
@@ -153,7 +147,7 @@ __device__ __forceinline__ int syrk_potrf_wave(const MB_GLOBAL double *Sm, size_
             store_tile(F, ldf, m, I, J, solve_right(a, w), fail_col, lr, lg);
         }
         // later block columns, and the next stage, read these tiles back
-        ric_fence();
+        wave_mem_sync();
         if (fail_col != INT_MAX)
             break;
     }

@@ -304,3 +304,33 @@ def test_riccati_argument_errors(L):
     assert L.riccati_workspace_size(4, 1, -1)[0] == -3
     assert L.lib.mb_riccati_workspace_size(4, 1, 1, None) == -4
     assert L.riccati_workspace_size(300, 5, 1)[0] == L.MB_ERR_UNSUPPORTED
+
+
+def test_trmm_syrk_argument_errors(L):
+    """Illegal arguments of the batched dtrmm_rlnn and dsyrk_ln return their
+    positions; quick returns succeed without a GPU."""
+    t = lambda *a: L.dtrmm_rlnn_strided_batched(*a)  # noqa: E731
+    ok = [5, 4, 1.0, P, 4, 16, P, 5, 20, 2, None]
+    for pos, val in ((0, -1), (1, -1), (4, 3), (5, -1), (7, 4), (8, 19), (9, -1)):
+        a = list(ok)
+        a[pos] = val
+        assert t(*a) == -(pos + 1), (pos, val)
+    for pos in (3, 6):
+        a = list(ok)
+        a[pos] = None
+        assert t(*a) == -(pos + 1)
+    assert t(0, 4, 1.0, None, 4, 0, None, 1, 0, 3, None) == 0
+    assert t(5, 4, 1.0, P, 4, 16, P, 5, 20, 0, None) == 0
+    s = lambda *a: L.dsyrk_ln_strided_batched(*a)  # noqa: E731
+    ok = [6, 3, 1.0, P, 6, 18, 0.5, P, 6, 36, 2, None]
+    for pos, val in ((0, -1), (1, -1), (4, 5), (5, -1), (8, 5), (9, 35), (10, -1)):
+        a = list(ok)
+        a[pos] = val
+        assert s(*a) == -(pos + 1), (pos, val)
+    for pos in (3, 7):
+        a = list(ok)
+        a[pos] = None
+        assert s(*a) == -(pos + 1)
+    assert s(6, 3, 0.0, None, 6, 18, 1.0, None, 6, 36, 2, None) == 0   # alpha 0, beta 1
+    assert s(6, 0, 1.0, None, 6, 18, 1.0, None, 6, 36, 2, None) == 0   # k 0, beta 1
+    assert s(0, 3, 1.0, None, 1, 0, 0.0, None, 1, 0, 2, None) == 0

@@ -196,3 +196,69 @@ def test_riccati_workspace_inplace_and_broadcast():
     Fh, LNh, infoh = _np(F), _np(LN), _np(info)
     for b in (0, batch - 1):
         _check_problem(Bh, Rh, _np(QN[0]), nu, Fh[b], LNh[b], infoh[b], f"broadcast b={b}")
+
+
+@pytest.mark.parametrize("m,n,alpha", [(12, 8, 1.0), (36, 24, -0.5), (96, 64, 1.0), (1, 1, 2.0),
+                                       (17, 33, 1.0), (40, 5, 0.0), (0, 4, 1.0)])
+def test_dtrmm_rlnn_vs_oracle(m, n, alpha):
+    """Batched dtrmm_rlnn against the oracle: A's upper triangle (NaN) is
+    never read, B's ld padding rows (NaN) never written, result within
+    RIC_TOL normwise."""
+    torch, _lib, blas = torch_mods()
+    batch, lda, ldb = 5, n + 3, m + 2
+    say(f"dtrmm_rlnn m={m} n={n} alpha={alpha}")
+    g = inputs.rng(inputs.seed_for(44, m * 100 + n))
+    A = g.uniform(-1, 1, size=(batch, max(n, 1), lda))
+    B = g.uniform(-1, 1, size=(batch, max(n, 1), ldb))
+    for b in range(batch):
+        for j in range(n):
+            A[b, j, :j] = np.nan          # strictly upper part of column j
+            A[b, j, n:] = np.nan
+        B[b, :, m:] = np.nan
+    dA = torch.from_numpy(A.copy()).cuda()
+    dB = torch.from_numpy(B.copy()).cuda()
+    st = _lib.dtrmm_rlnn_strided_batched(m, n, alpha, dA.data_ptr(), lda, A[0].size, dB.data_ptr(),
+                                         ldb, B[0].size, batch,
+                                         torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    got = _np(dB)
+    for b in range(batch):
+        Bo = np.asfortranarray(B[b].T[:m, :n])
+        Ao = np.asfortranarray(A[b].T[:n, :n])
+        oracle.dtrmm_rlnn(alpha, Ao, Bo)
+        g_b = got[b].T
+        assert np.all(np.isnan(g_b[m:, :n])), "padding written"
+        assert _rel(g_b[:m, :n], Bo) <= RIC_TOL or np.max(np.abs(g_b[:m, :n] - Bo)) == 0.0
+
+
+@pytest.mark.parametrize("n,k,alpha,beta", [(12, 8, 1.0, 1.0), (36, 24, -1.0, 0.5),
+                                            (96, 64, 1.0, 1.0), (33, 17, 2.0, 0.0),
+                                            (5, 0, 1.0, 2.0), (20, 3, 0.0, -1.0), (1, 1, 1.0, 1.0)])
+def test_dsyrk_ln_vs_oracle(n, k, alpha, beta):
+    """Batched dsyrk_ln against the oracle: strictly upper triangle (NaN)
+    untouched, beta == 0 does not read C, lower triangle within RIC_TOL."""
+    torch, _lib, blas = torch_mods()
+    batch, lda, ldc = 4, n + 1, n + 2
+    say(f"dsyrk_ln n={n} k={k} alpha={alpha} beta={beta}")
+    g = inputs.rng(inputs.seed_for(45, n * 100 + k))
+    A = g.uniform(-1, 1, size=(batch, max(k, 1), lda))
+    C = g.uniform(-1, 1, size=(batch, max(n, 1), ldc))
+    for b in range(batch):
+        for j in range(n):
+            C[b, j, :j] = np.nan
+            if beta == 0.0:
+                C[b, j, j:n] = np.nan
+    dA = torch.from_numpy(A.copy()).cuda()
+    dC = torch.from_numpy(C.copy()).cuda()
+    st = _lib.dsyrk_ln_strided_batched(n, k, alpha, dA.data_ptr(), lda, A[0].size, beta,
+                                       dC.data_ptr(), ldc, C[0].size, batch,
+                                       torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    got = _np(dC)
+    lo, up = np.tril_indices(n), np.triu_indices(n, 1)
+    for b in range(batch):
+        Co = np.asfortranarray(C[b].T[:n, :n])
+        oracle.dsyrk_ln(alpha, np.asfortranarray(A[b].T[:n, :k]), beta, Co)
+        g_b = got[b].T[:n, :n]
+        assert np.all(np.isnan(g_b[up])), "upper triangle written"
+        assert _rel(g_b[lo], Co[lo]) <= RIC_TOL or np.max(np.abs(g_b[lo] - Co[lo])) == 0.0
