@@ -49,45 +49,70 @@ struct PotrfSmem {
     int fail;            // first failing global column, INT_MAX if none
 };
 
+// 1/sqrt(a) for a positive normal a: the hardware estimate refined by two
+// Newton-Raphson steps for f(y) = 1/y^2 - a, y <- y + y (1 - a y^2) / 2
+// (quadratic convergence; the result is within a few ulp of the exact value).
+__device__ __forceinline__ double rsqrt_nr(double a)
+{
+    double y = __builtin_amdgcn_rsq(a);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double e = fma(-(a * y), y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
 // Factor one 16x16 diagonal tile held in accumulator order -- lane (g, i),
 // register r holds T[i][g + 4r] -- by one whole wave (inner_edge_dpotrf).
-// Column c is eliminated in step c: its current values are published through
-// LDS, every lane forms l_ic = T[i][c]/l_cc for its row and l_qc for its four
-// columns q, and updates its own entries T[i][q] -= l_ic*l_qc (c < q <= i).
-// Alongside, X = L^{-1} is accumulated in the same order as the product of
-// inverted column factors (X <= C_c^{-1} X with C_c the identity except for
-// column c of L): row c is scaled by 1/l_cc and rows i > c lose l_ic times it.
-// Row c of X is published with column c+1 of T, so each step costs a single
-// LDS round trip.  A failing pivot at column c is recorded in S.fail; columns
-// c..15 are then replaced by the identity so that L stays invertible.
-// On exit t holds L (upper part zero) and x holds L^{-1}, both in accumulator
-// order -- which is exactly the left-operand order the panel MFMA needs.
-template <class Smem>
-__device__ __forceinline__ void factor_diag_tile(d4 &t, d4 &x, Smem &S, int J, int lane)
+// Column c is eliminated in step c: its entries on and below the diagonal are
+// published through LDS (zeros above it), every lane forms
+// l_ic = T[i][c] / sqrt(t_cc) for its row and updates its four entries
+// T[i][q] -= l_ic * l_qc.  The published zeros make the update a no-op for
+// the finished columns q < c, and the entries above the diagonal that it
+// touches are cleared at the end, so no lane needs a mask.  With INV,
+// X = L^{-1} is accumulated alongside as the product of inverted column
+// factors (X <= C_c^{-1} X, C_c the identity except for column c of L): row c
+// is scaled by 1/l_cc and rows i > c lose l_ic times it; row c of X is
+// published with column c+1 of T, so each step costs a single LDS round trip.
+// Only the first `cols` columns are eliminated: the rest of the tile is the
+// identity padding of an order that is not a multiple of 16.  A failing pivot
+// at column c is recorded in S.fail; columns c..15 then become the identity
+// so that L stays invertible.  On exit t holds L (upper part zero) and, with
+// INV, x holds L^{-1}, both in accumulator order -- exactly the left-operand
+// order the panel MFMA needs.
+template <bool INV, class Smem>
+__device__ __forceinline__ void factor_diag_tile(d4 &t, d4 &x, Smem &S, int J, int lane,
+                                                 int cols = 16)
 {
     const int i = lane & 15, g = lane >> 4;
+    if (INV) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        x[r] = (i == g + 4 * r) ? 1.0 : 0.0;
+        for (int r = 0; r < 4; ++r)
+            x[r] = (i == g + 4 * r) ? 1.0 : 0.0;
+    }
     bool failed = false;
-    double lic_prev = 0.0;  // l_{i,c-1} of the previous step
+    double lprev = 0.0;  // l_{i,c-1} of the previous step for rows i > c-1, else 0
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
+        if (c >= cols)
+            break;
         const int buf = c & 1;
-        // publish column c of T and (from step 1 on) the scaled row c-1 of X
+        // publish column c of T (on and below the diagonal) and, from step 1
+        // on, the scaled row c-1 of X
         if (g == (c & 3))
-            S.col[buf][i] = t[c >> 2];
-        if (c > 0 && i == c - 1) {
+            S.col[buf][i] = (i >= c) ? t[c >> 2] : 0.0;
+        if (INV && c > 0 && i == c - 1) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 S.xrow[buf][g + 4 * r] = x[r];
         }
         wave_lds_sync();
         // X update of step c-1: rows i > c-1 lose l_{i,c-1} * (scaled row c-1)
-        if (c > 0 && i > c - 1) {
+        if (INV && c > 0) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                x[r] = fma(-lic_prev, S.xrow[buf][g + 4 * r], x[r]);
+                x[r] = fma(-lprev, S.xrow[buf][g + 4 * r], x[r]);
         }
         const double piv = S.col[buf][c];
         if (!failed && !(piv > 0.0)) {
@@ -95,35 +120,28 @@ __device__ __forceinline__ void factor_diag_tile(d4 &t, d4 &x, Smem &S, int J, i
             if (lane == 0)
                 S.fail = 16 * J + c;
         }
-        double ljj = 1.0, rinv = 1.0;
+        double rinv = 1.0, li;
         if (!failed) {
-            ljj = sqrt(piv);
-            rinv = 1.0 / ljj;
-        }
-        // l_ic for this lane's row (zero above the diagonal and after a failure)
-        double lic;
-        if (i == c)
-            lic = ljj;
-        else if (i > c && !failed)
-            lic = S.col[buf][i] * rinv;
-        else
-            lic = 0.0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int q = g + 4 * r;
-            if (q > c && q <= i && !failed)
-                t[r] = fma(-lic, S.col[buf][q] * rinv, t[r]);
-        }
-        if (g == (c & 3))
-            t[c >> 2] = (i >= c) ? lic : 0.0;
-        if (i == c) {
+            rinv = rsqrt_nr(piv);
+            li = S.col[buf][i] * rinv;  // l_cc = t_cc / sqrt(t_cc) on the diagonal
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                x[r] *= rinv;
+                t[r] = fma(-li, S.col[buf][g + 4 * r] * rinv, t[r]);
+        } else {
+            li = (i == c) ? 1.0 : 0.0;
         }
-        lic_prev = (i > c) ? lic : 0.0;
+        if (g == (c & 3))
+            t[c >> 2] = li;
+        if (INV) {
+            if (i == c) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    x[r] *= rinv;
+            }
+            lprev = (i > c) ? li : 0.0;
+        }
     }
-    // zero the strict upper part of L (entries of T never touched above)
+    // zero the strict upper part of L
 #pragma unroll
     for (int r = 0; r < 4; ++r)
         if (g + 4 * r > i)
@@ -235,7 +253,7 @@ __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT
             }
         }
         d4 w0, w1 = d4{0.0, 0.0, 0.0, 0.0};
-        factor_diag_tile(t00, w0, S, J, lane);
+        factor_diag_tile<true>(t00, w0, S, J, lane, n - 16 * J);
         wave_lds_sync();
         int fail_col = S.fail;
         store_diag(A, lda, n, J, t00, fail_col, lr, lg);
@@ -245,7 +263,7 @@ __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT
             store_tile(A, lda, n, J1, J, l10, fail_col, lr, lg);
             if (fail_col == INT_MAX) {
                 t11 = update_nt(t11, l10, l10);
-                factor_diag_tile(t11, w1, S, J1, lane);
+                factor_diag_tile<true>(t11, w1, S, J1, lane, n - 16 * J1);
                 wave_lds_sync();
                 fail_col = S.fail;
                 store_diag(A, lda, n, J1, t11, fail_col, lr, lg);

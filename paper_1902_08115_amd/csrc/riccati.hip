@@ -23,7 +23,8 @@
 //      diagonal tile factored in registers (factor_diag_tile) and the panel
 //      solved against its inverse -- the structure of potrf_wave.h, with the
 //      syrk terms in the same accumulation.
-// The grid is a fixed set of waves (at most what the device holds at once),
+// Problems with nu + nx <= 16 take a register-resident variant (below).
+// Otherwise the grid is a fixed set of waves (at most what the device holds at once),
 // each owning one workspace slot and taking problems b = w, w + W, ... in
 // turn; all problems have the same shape, so the static split is balanced,
 // and a slot is rewritten problem after problem while it is still cached.
@@ -90,6 +91,12 @@ __device__ __forceinline__ void ws_store(MB_GLOBAL double *W, int ntk, int I, in
     p[192] = t[3];
 }
 
+// The inner sums below take their operand tiles RIC_CHUNK at a time, all
+// loads of a chunk issued before its first MFMA, so that one memory latency
+// covers RIC_CHUNK tile products; indices past the end are clamped (a cached
+// reload) and their products skipped.
+constexpr int RIC_CHUNK = 4;
+
 // C = BAt * L into the workspace: BAt is m x nx, L the nx x nx lower factor;
 // ntm = ceil(m / 16) by ntx = ceil(nx / 16) tiles, zero outside m x nx.
 __device__ __forceinline__ void trmm_wave(const MB_GLOBAL double *BAt, size_t ldb, const MB_GLOBAL double *L,
@@ -100,14 +107,62 @@ __device__ __forceinline__ void trmm_wave(const MB_GLOBAL double *BAt, size_t ld
     for (int I = 0; I < ntm; ++I)
         for (int K = 0; K < ntx; ++K) {
             d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-            for (int T = K; T < ntx; ++T) {
-                const d4 x = load_rect(BAt, ldb, m, nx, I, T, lr, lg);
-                const d4 y = load_lower_t(L, ldl, nx, T, K, lr, lg);
-                acc = add_xyT(acc, x, y);
+            for (int T0 = K; T0 < ntx; T0 += RIC_CHUNK) {
+                d4 x[RIC_CHUNK], y[RIC_CHUNK];
+#pragma unroll
+                for (int u = 0; u < RIC_CHUNK; ++u) {
+                    const int T = min(T0 + u, ntx - 1);
+                    x[u] = load_rect(BAt, ldb, m, nx, I, T, lr, lg);
+                    y[u] = load_lower_t(L, ldl, nx, T, K, lr, lg);
+                }
+#pragma unroll
+                for (int u = 0; u < RIC_CHUNK; ++u)
+                    if (T0 + u < ntx)
+                        acc = add_xyT(acc, x[u], y[u]);
             }
             ws_store(W, ntx, I, K, acc, lane);
         }
     wave_mem_sync();
+}
+
+// acc + sum_{K < ntk} C(I,K) C(J,K)^T from the workspace.
+__device__ __forceinline__ d4 syrk_terms(d4 acc, const MB_GLOBAL double *W, int ntk, int I, int J,
+                                         int lane)
+{
+    for (int K0 = 0; K0 < ntk; K0 += RIC_CHUNK) {
+        d4 a[RIC_CHUNK], b[RIC_CHUNK];
+#pragma unroll
+        for (int u = 0; u < RIC_CHUNK; ++u) {
+            const int K = min(K0 + u, ntk - 1);
+            a[u] = ws_load(W, ntk, I, K, lane);
+            b[u] = I == J ? a[u] : ws_load(W, ntk, J, K, lane);
+        }
+#pragma unroll
+        for (int u = 0; u < RIC_CHUNK; ++u)
+            if (K0 + u < ntk)
+                acc = add_xyT(acc, a[u], b[u]);
+    }
+    return acc;
+}
+
+// acc - sum_{K < J} F(I,K) F(J,K)^T from the factor already written.
+__device__ __forceinline__ d4 potrf_terms(d4 acc, const MB_GLOBAL double *F, size_t ldf, int m, int I,
+                                          int J, int lr, int lg)
+{
+    for (int K0 = 0; K0 < J; K0 += RIC_CHUNK) {
+        d4 a[RIC_CHUNK], b[RIC_CHUNK];
+#pragma unroll
+        for (int u = 0; u < RIC_CHUNK; ++u) {
+            const int K = min(K0 + u, J - 1);
+            a[u] = load_tile(F, ldf, m, I, K, lr, lg, false);
+            b[u] = I == J ? a[u] : load_tile(F, ldf, m, J, K, lr, lg, false);
+        }
+#pragma unroll
+        for (int u = 0; u < RIC_CHUNK; ++u)
+            if (K0 + u < J)
+                acc = update_nt(acc, a[u], b[u]);
+    }
+    return acc;
 }
 
 // F = chol(S + C C^T) for the m x m symmetric S (lower triangle read) and the
@@ -124,26 +179,15 @@ __device__ __forceinline__ int syrk_potrf_wave(const MB_GLOBAL double *Sm, size_
     wave_lds_sync();
     for (int J = 0; J < nt; ++J) {
         d4 t = load_tile(Sm, lds, m, J, J, lr, lg, true);
-        for (int K = 0; K < ntk; ++K) {
-            const d4 c = ws_load(W, ntk, J, K, lane);
-            t = add_xyT(t, c, c);
-        }
-        for (int K = 0; K < J; ++K) {
-            const d4 l = load_tile(F, ldf, m, J, K, lr, lg, false);
-            t = update_nt(t, l, l);
-        }
+        t = potrf_terms(syrk_terms(t, W, ntk, J, J, lane), F, ldf, m, J, J, lr, lg);
         d4 w;
-        factor_diag_tile(t, w, S, J, lane);
+        factor_diag_tile<true>(t, w, S, J, lane, m - 16 * J);
         wave_lds_sync();
         const int fail_col = S.fail;
         store_diag(F, ldf, m, J, t, fail_col, lr, lg);
         for (int I = J + 1; I < nt; ++I) {
             d4 a = load_tile(Sm, lds, m, I, J, lr, lg, false);
-            for (int K = 0; K < ntk; ++K)
-                a = add_xyT(a, ws_load(W, ntk, I, K, lane), ws_load(W, ntk, J, K, lane));
-            for (int K = 0; K < J; ++K)
-                a = update_nt(a, load_tile(F, ldf, m, I, K, lr, lg, false),
-                              load_tile(F, ldf, m, J, K, lr, lg, false));
+            a = potrf_terms(syrk_terms(a, W, ntk, I, J, lane), F, ldf, m, I, J, lr, lg);
             store_tile(F, ldf, m, I, J, solve_right(a, w), fail_col, lr, lg);
         }
         // later block columns, and the next stage, read these tiles back
@@ -193,6 +237,90 @@ __global__ __launch_bounds__(RIC_WPB * 64) void riccati_kernel(RiccatiArgs p, in
     }
 }
 
+// Problems with m = nu + nx <= 16: every stage is one 16 x 16 tile, and the
+// whole recursion stays in the wave's registers.  The next stage's BAt and
+// RSQ tiles are loaded while the current stage is factored; the factor of
+// P_n -- needed transposed by the next stage's dtrmm -- goes from the
+// factored tile to the next operand through LDS, so stages exchange nothing
+// through global memory (F is only written).
+struct RicSmallSmem {
+    PotrfSmem potrf;
+    double t[16][17];  // factored tile, for the shifted transpose
+};
+
+// Y with Y[i][c] = F(nu + c, nu + i) for c, i < nx (else 0): the next dtrmm
+// operand (the transpose of the bottom-right nx x nx block) of the factored
+// tile f, held in accumulator order.
+__device__ __forceinline__ d4 next_operand(const d4 &f, RicSmallSmem &S, int nx, int nu, int lane)
+{
+    const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        S.t[i][g + 4 * r] = f[r];
+    wave_lds_sync();
+    d4 y;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int c = g + 4 * r;
+        y[r] = (i < nx && c < nx) ? S.t[nu + c][nu + i] : 0.0;
+    }
+    wave_lds_sync();
+    return y;
+}
+
+__global__ __launch_bounds__(RIC_WPB * 64) void riccati_small_kernel(RiccatiArgs p)
+{
+    __shared__ RicSmallSmem smem[RIC_WPB];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t b = (int64_t)blockIdx.x * RIC_WPB + wave;
+    if (b >= p.batch)
+        return;
+    RicSmallSmem &S = smem[wave];
+    const int lr = lane & 15, lg = lane >> 4;
+    const int nx = p.nx, nu = p.nu, N = p.N, m = nx + nu;
+    MB_GLOBAL int *info = global_ptr(p.info) + b * (N + 1);
+    const MB_GLOBAL double *BAt = global_ptr(p.BAt) + b * p.sBAt;
+    const MB_GLOBAL double *RSQ = global_ptr(p.RSQ) + b * p.sRSQ;
+    MB_GLOBAL double *F = global_ptr(p.F) + b * p.sF;
+
+    MB_GLOBAL double *LN = global_ptr(p.LN) + b * p.sL;
+    // Iteration n = N factors Q_N (its dtrmm operand is zero); iterations
+    // n < N are the stages.  The operands of iteration n - 1 are loaded while
+    // iteration n runs.
+    d4 x_next = d4{0.0, 0.0, 0.0, 0.0}, y = x_next;
+    d4 r_next = load_tile(global_ptr(p.QN) + b * p.sQ, (size_t)p.ldq, nx, 0, 0, lr, lg, true);
+    int n = N, st = 0;
+    for (; n >= 0; --n) {
+        const d4 x = x_next, rq = r_next;
+        if (n > 0) {
+            x_next = load_rect(BAt + (n - 1) * p.stBAt, (size_t)p.ldbat, m, nx, 0, 0, lr, lg);
+            r_next = load_tile(RSQ + (n - 1) * p.stRSQ, (size_t)p.ldrsq, m, 0, 0, lr, lg, true);
+        }
+        const d4 c = add_xyT(d4{0.0, 0.0, 0.0, 0.0}, x, y);  // C_n = BAt_n Lc_{n+1}
+        d4 f = add_xyT(rq, c, c);                            // RSQ_n + C_n C_n^T
+        if (lane == 0)
+            S.potrf.fail = INT_MAX;
+        wave_lds_sync();
+        d4 w;
+        factor_diag_tile<false>(f, w, S.potrf, 0, lane, n == N ? nx : m);
+        wave_lds_sync();
+        const int fail = S.potrf.fail;
+        const bool term = n == N;
+        store_diag(term ? LN : F + n * p.stF, term ? (size_t)p.ldl : (size_t)p.ldf, term ? nx : m, 0, f,
+                   fail, lr, lg);
+        st = fail == INT_MAX ? 0 : fail + 1;
+        if (lane == 0)
+            info[n] = st;
+        if (st != 0)
+            break;
+        y = next_operand(f, S, nx, term ? 0 : nu, lane);
+    }
+    // stages below a failure are not computed
+    for (int q = lane; q < n; q += 64)
+        info[q] = -1;
+}
+
 int64_t riccati_slot_doubles(int nx, int nu)
 {
     const int64_t ntm = (nx + nu + 15) / 16, ntx = (nx + 15) / 16;
@@ -215,6 +343,12 @@ hipError_t riccati_max_waves(int *waves)
 
 hipError_t launch_riccati(const RiccatiArgs &a, int waves, hipStream_t s)
 {
+    if (a.nx + a.nu <= 16) {
+        const int64_t blocks = (a.batch + RIC_WPB - 1) / RIC_WPB;
+        hipLaunchKernelGGL(riccati_small_kernel, dim3((unsigned)blocks), dim3(RIC_WPB * 64), 0, s,
+                           a);
+        return hipGetLastError();
+    }
     const unsigned blocks = (unsigned)((waves + RIC_WPB - 1) / RIC_WPB);
     hipLaunchKernelGGL(riccati_kernel, dim3(blocks), dim3(RIC_WPB * 64), 0, s, a, waves);
     return hipGetLastError();
