@@ -17,7 +17,11 @@ __global__ __launch_bounds__(IPB * 64) __attribute__((amdgpu_waves_per_eu(2))) v
     if (b >= p.batch)
         return;  // each wave is its own instance: nothing to synchronise with
     double *A = inst_ptr(p.A, p.Aarr, p.sA, b);
-    const int info = potrf_wave<true>(A, (size_t)p.lda, p.n, NT, smem[inst], lane);
+    // the pipelined update loops need more registers; they measured faster at
+    // n = 256 and slower at n = 64, 128 and 192 (same occupancy or one wave
+    // per SIMD less), so only the largest orders use them
+    constexpr bool PIPE = NT >= 16;
+    const int info = potrf_wave<true, 2, PIPE>(A, (size_t)p.lda, p.n, NT, smem[inst], lane);
     if (lane == 0)
         p.info[b] = info;
 }

@@ -219,7 +219,7 @@ __device__ __forceinline__ d4 update_nt(d4 acc, const d4 &x, const d4 &y)
 // Factor the n x n lower triangle of A (nt = ceil(n / 16) tiles) with the
 // calling wave; returns the LAPACK info (0, or the failing column + 1).  S is
 // this wave's private LDS block.
-template <bool PAIR, int G = 2>
+template <bool PAIR, int G = 2, bool PIPE = true>
 __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT, PotrfSmem &S,
                                           int lane)
 {
@@ -243,13 +243,36 @@ __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT
             t10 = load_tile(A, lda, n, J1, J, lr, lg, false);
             t11 = load_tile(A, lda, n, J1, J1, lr, lg, true);
         }
-        for (int K = 0; K < J; ++K) {
-            const d4 l0 = load_tile(A, lda, n, J, K, lr, lg, false);
-            t00 = update_nt(t00, l0, l0);
-            if (two) {
-                const d4 l1 = load_tile(A, lda, n, J1, K, lr, lg, false);
-                t10 = update_nt(t10, l1, l0);
-                t11 = update_nt(t11, l1, l1);
+        // The update loops below are software-pipelined: the tiles of step
+        // K + 1 are loaded while the MFMAs of step K run (the index is clamped
+        // at the last step -- a cached reload instead of a branch).  Row tile
+        // NT lies past the matrix and loads as zeros without a memory access,
+        // which stands in for J1 when there is no second column.
+        // (PIPE = false keeps the plain loops, which need fewer registers.)
+        const int R1 = two ? J1 : NT;
+        if (!PIPE) {
+            for (int K = 0; K < J; ++K) {
+                const d4 l0 = load_tile(A, lda, n, J, K, lr, lg, false);
+                t00 = update_nt(t00, l0, l0);
+                if (two) {
+                    const d4 l1 = load_tile(A, lda, n, J1, K, lr, lg, false);
+                    t10 = update_nt(t10, l1, l0);
+                    t11 = update_nt(t11, l1, l1);
+                }
+            }
+        } else if (J > 0) {
+            d4 p0 = load_tile(A, lda, n, J, 0, lr, lg, false);
+            d4 p1 = load_tile(A, lda, n, R1, 0, lr, lg, false);
+            for (int K = 0; K < J; ++K) {
+                const d4 l0 = p0, l1 = p1;
+                const int Kn = min(K + 1, J - 1);
+                p0 = load_tile(A, lda, n, J, Kn, lr, lg, false);
+                p1 = load_tile(A, lda, n, R1, Kn, lr, lg, false);
+                t00 = update_nt(t00, l0, l0);
+                if (two) {
+                    t10 = update_nt(t10, l1, l0);
+                    t11 = update_nt(t11, l1, l1);
+                }
             }
         }
         d4 w0, w1 = d4{0.0, 0.0, 0.0, 0.0};
@@ -279,17 +302,47 @@ __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT
                 a1[g] = (in && two) ? load_tile(A, lda, n, I0 + g, J1, lr, lg, false)
                                     : d4{0.0, 0.0, 0.0, 0.0};
             }
-            for (int K = 0; K < J; ++K) {
-                const d4 l0 = load_tile(A, lda, n, J, K, lr, lg, false);
-                const d4 l1 = two ? load_tile(A, lda, n, J1, K, lr, lg, false)
-                                  : d4{0.0, 0.0, 0.0, 0.0};
+            if (!PIPE) {
+                for (int K = 0; K < J; ++K) {
+                    const d4 l0 = load_tile(A, lda, n, J, K, lr, lg, false);
+                    const d4 l1 = two ? load_tile(A, lda, n, J1, K, lr, lg, false)
+                                      : d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    if (I0 + g < NT) {
-                        const d4 li = load_tile(A, lda, n, I0 + g, K, lr, lg, false);
-                        a0[g] = update_nt(a0[g], li, l0);
-                        if (two)
-                            a1[g] = update_nt(a1[g], li, l1);
+                    for (int g = 0; g < G; ++g) {
+                        if (I0 + g < NT) {
+                            const d4 li = load_tile(A, lda, n, I0 + g, K, lr, lg, false);
+                            a0[g] = update_nt(a0[g], li, l0);
+                            if (two)
+                                a1[g] = update_nt(a1[g], li, l1);
+                        }
+                    }
+                }
+            } else if (J > 0) {
+                d4 p0 = load_tile(A, lda, n, J, 0, lr, lg, false);
+                d4 p1 = load_tile(A, lda, n, R1, 0, lr, lg, false);
+                d4 pi[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    pi[g] = load_tile(A, lda, n, I0 + g, 0, lr, lg, false);
+                for (int K = 0; K < J; ++K) {
+                    const d4 l0 = p0, l1 = p1;
+                    d4 li[G];
+#pragma unroll
+                    for (int g = 0; g < G; ++g)
+                        li[g] = pi[g];
+                    const int Kn = min(K + 1, J - 1);
+                    p0 = load_tile(A, lda, n, J, Kn, lr, lg, false);
+                    p1 = load_tile(A, lda, n, R1, Kn, lr, lg, false);
+#pragma unroll
+                    for (int g = 0; g < G; ++g)
+                        pi[g] = load_tile(A, lda, n, I0 + g, Kn, lr, lg, false);
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        if (I0 + g < NT) {
+                            a0[g] = update_nt(a0[g], li[g], l0);
+                            if (two)
+                                a1[g] = update_nt(a1[g], li[g], l1);
+                        }
                     }
                 }
             }
