@@ -21,7 +21,9 @@ __global__ __launch_bounds__(IPB * 64) __attribute__((amdgpu_waves_per_eu(2))) v
     // n = 256 and slower at n = 64, 128 and 192 (same occupancy or one wave
     // per SIMD less), so only the largest orders use them
     constexpr bool PIPE = NT >= 16;
-    const int info = potrf_wave<true, 2, PIPE>(A, (size_t)p.lda, p.n, NT, smem[inst], lane);
+    // one tile: the unrolled diagonal factorization costs no occupancy there
+    constexpr bool UNROLL = NT == 1;
+    const int info = potrf_wave<true, 2, PIPE, UNROLL>(A, (size_t)p.lda, p.n, NT, smem[inst], lane);
     if (lane == 0)
         p.info[b] = info;
 }

@@ -80,8 +80,10 @@ __device__ __forceinline__ double rsqrt_nr(double a)
 // at column c is recorded in S.fail; columns c..15 then become the identity
 // so that L stays invertible.  On exit t holds L (upper part zero) and, with
 // INV, x holds L^{-1}, both in accumulator order -- exactly the left-operand
-// order the panel MFMA needs.
-template <bool INV, class Smem>
+// order the panel MFMA needs.  UNROLL unrolls the 16 steps (about half the
+// instructions per step, since register indices become constants, but more
+// registers): for kernels whose occupancy does not suffer from it.
+template <bool INV, bool UNROLL = false, class Smem>
 __device__ __forceinline__ void factor_diag_tile(d4 &t, d4 &x, Smem &S, int J, int lane,
                                                  int cols = 16)
 {
@@ -95,8 +97,11 @@ __device__ __forceinline__ void factor_diag_tile(d4 &t, d4 &x, Smem &S, int J, i
     double lprev = 0.0;  // l_{i,c-1} of the previous step for rows i > c-1, else 0
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
-        if (c >= cols)
-            break;
+        if (c >= cols) {
+            if (UNROLL)
+                continue;  // the loop stays fully unrolled: c is a constant in every step
+            break;         // a rolled loop: fewer registers, more instructions per step
+        }
         const int buf = c & 1;
         // publish column c of T (on and below the diagonal) and, from step 1
         // on, the scaled row c-1 of X
@@ -219,7 +224,7 @@ __device__ __forceinline__ d4 update_nt(d4 acc, const d4 &x, const d4 &y)
 // Factor the n x n lower triangle of A (nt = ceil(n / 16) tiles) with the
 // calling wave; returns the LAPACK info (0, or the failing column + 1).  S is
 // this wave's private LDS block.
-template <bool PAIR, int G = 2, bool PIPE = true>
+template <bool PAIR, int G = 2, bool PIPE = true, bool UNROLL = false>
 __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT, PotrfSmem &S,
                                           int lane)
 {
@@ -276,7 +281,7 @@ __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT
             }
         }
         d4 w0, w1 = d4{0.0, 0.0, 0.0, 0.0};
-        factor_diag_tile<true>(t00, w0, S, J, lane, n - 16 * J);
+        factor_diag_tile<true, UNROLL>(t00, w0, S, J, lane, n - 16 * J);
         wave_lds_sync();
         int fail_col = S.fail;
         store_diag(A, lda, n, J, t00, fail_col, lr, lg);
@@ -286,7 +291,7 @@ __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT
             store_tile(A, lda, n, J1, J, l10, fail_col, lr, lg);
             if (fail_col == INT_MAX) {
                 t11 = update_nt(t11, l10, l10);
-                factor_diag_tile<true>(t11, w1, S, J1, lane, n - 16 * J1);
+                factor_diag_tile<true, UNROLL>(t11, w1, S, J1, lane, n - 16 * J1);
                 wave_lds_sync();
                 fail_col = S.fail;
                 store_diag(A, lda, n, J1, t11, fail_col, lr, lg);
