@@ -614,7 +614,7 @@ int mb_riccati_workspace_size(int nx, int nu, int batch, size_t *bytes)
     if (!bytes) return -4;
     if (nx + nu > mb::POTRF_MAX_N) return MB_ERR_UNSUPPORTED;
     int waves = 0;
-    const hipError_t e = mb::riccati_max_waves(&waves);
+    const hipError_t e = mb::riccati_max_waves(nx, nu, &waves);
     if (e != hipSuccess)
         return MB_ERR_HIP;
     const int64_t w = std::max<int64_t>(1, std::min<int64_t>(batch, waves));
@@ -664,7 +664,7 @@ int mb_riccati_strided_batched(int nx, int nu, int N, const double *BAt, int ldb
     if (slot > 0 && !work) return -23;
     if (slots < 1) return -24;
     int waves = 0;
-    hipError_t e = mb::riccati_max_waves(&waves);
+    hipError_t e = mb::riccati_max_waves(nx, nu, &waves);
     if (e != hipSuccess)
         return MB_ERR_HIP;
     waves = (int)std::min<int64_t>(std::min<int64_t>(waves, slots), batch);

@@ -256,7 +256,7 @@ hipError_t launch_scatter_info(const int *src, int *const *dst, int count, hipSt
 hipError_t launch_trmm_rlnn(const TrmmArgs &a, hipStream_t s);
 hipError_t launch_syrk_ln(const SyrkArgs &a, hipStream_t s);
 int64_t riccati_slot_doubles(int nx, int nu);  // workspace of one wave
-hipError_t riccati_max_waves(int *waves);      // waves resident at once on the device
+hipError_t riccati_max_waves(int nx, int nu, int *waves);  // waves resident at once
 hipError_t launch_riccati(const RiccatiArgs &a, int waves, hipStream_t s);
 
 // Validated dgemm / dpotrf launches used by the C ABI and by plans (api.hip):

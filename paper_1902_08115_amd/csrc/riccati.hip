@@ -30,6 +30,8 @@
 // and a slot is rewritten problem after problem while it is still cached.
 #include <limits.h>
 
+#include <type_traits>
+
 #include "potrf_wave.h"
 
 namespace mb {
@@ -75,21 +77,47 @@ __device__ __forceinline__ d4 load_lower_t(const MB_GLOBAL double *L, size_t ld,
     return t;
 }
 
-// Workspace tile (I, K) of C: register r of lane l at tile * 256 + r * 64 + l.
-__device__ __forceinline__ d4 ws_load(const MB_GLOBAL double *W, int ntk, int I, int K, int lane)
-{
-    const MB_GLOBAL double *p = W + ((size_t)I * ntk + K) * 256 + lane;
-    return d4{p[0], p[64], p[128], p[192]};
-}
-__device__ __forceinline__ void ws_store(MB_GLOBAL double *W, int ntk, int I, int K, const d4 &t,
-                                         int lane)
-{
-    MB_GLOBAL double *p = W + ((size_t)I * ntk + K) * 256 + lane;
-    p[0] = t[0];
-    p[64] = t[1];
-    p[128] = t[2];
-    p[192] = t[3];
-}
+// Where C lives: tile (I, K) of C holds register r of lane l at
+// (I * ntk + K) * 256 + r * 64 + l, either in the wave's slot of the global
+// workspace or, when the tiles fit, in the wave's part of LDS.  Each lane
+// reads back only what it wrote, so after the dtrmm a wave-level fence
+// suffices (global: the stores must complete; LDS: the LDS counter).
+struct GlobalC {
+    MB_GLOBAL double *W;
+    int ntk;
+    __device__ __forceinline__ d4 load(int I, int K, int lane) const
+    {
+        const MB_GLOBAL double *p = W + ((size_t)I * ntk + K) * 256 + lane;
+        return d4{p[0], p[64], p[128], p[192]};
+    }
+    __device__ __forceinline__ void store(int I, int K, const d4 &t, int lane) const
+    {
+        MB_GLOBAL double *p = W + ((size_t)I * ntk + K) * 256 + lane;
+        p[0] = t[0];
+        p[64] = t[1];
+        p[128] = t[2];
+        p[192] = t[3];
+    }
+    __device__ __forceinline__ void sync() const { wave_mem_sync(); }
+};
+struct LdsC {
+    double *W;  // this wave's LDS block
+    int ntk;
+    __device__ __forceinline__ d4 load(int I, int K, int lane) const
+    {
+        const double *p = W + (I * ntk + K) * 256 + lane;
+        return d4{p[0], p[64], p[128], p[192]};
+    }
+    __device__ __forceinline__ void store(int I, int K, const d4 &t, int lane) const
+    {
+        double *p = W + (I * ntk + K) * 256 + lane;
+        p[0] = t[0];
+        p[64] = t[1];
+        p[128] = t[2];
+        p[192] = t[3];
+    }
+    __device__ __forceinline__ void sync() const { wave_lds_sync(); }
+};
 
 // The inner sums below take their operand tiles RIC_CHUNK at a time, all
 // loads of a chunk issued before its first MFMA, so that one memory latency
@@ -99,9 +127,10 @@ constexpr int RIC_CHUNK = 4;
 
 // C = BAt * L into the workspace: BAt is m x nx, L the nx x nx lower factor;
 // ntm = ceil(m / 16) by ntx = ceil(nx / 16) tiles, zero outside m x nx.
+template <class CS>
 __device__ __forceinline__ void trmm_wave(const MB_GLOBAL double *BAt, size_t ldb, const MB_GLOBAL double *L,
-                                          size_t ldl, int m, int nx, int ntm, int ntx,
-                                          MB_GLOBAL double *W, int lane)
+                                          size_t ldl, int m, int nx, int ntm, int ntx, const CS &W,
+                                          int lane)
 {
     const int lr = lane & 15, lg = lane >> 4;
     for (int I = 0; I < ntm; ++I)
@@ -120,22 +149,22 @@ __device__ __forceinline__ void trmm_wave(const MB_GLOBAL double *BAt, size_t ld
                     if (T0 + u < ntx)
                         acc = add_xyT(acc, x[u], y[u]);
             }
-            ws_store(W, ntx, I, K, acc, lane);
+            W.store(I, K, acc, lane);
         }
-    wave_mem_sync();
+    W.sync();
 }
 
-// acc + sum_{K < ntk} C(I,K) C(J,K)^T from the workspace.
-__device__ __forceinline__ d4 syrk_terms(d4 acc, const MB_GLOBAL double *W, int ntk, int I, int J,
-                                         int lane)
+// acc + sum_{K < ntk} C(I,K) C(J,K)^T.
+template <class CS>
+__device__ __forceinline__ d4 syrk_terms(d4 acc, const CS &W, int ntk, int I, int J, int lane)
 {
     for (int K0 = 0; K0 < ntk; K0 += RIC_CHUNK) {
         d4 a[RIC_CHUNK], b[RIC_CHUNK];
 #pragma unroll
         for (int u = 0; u < RIC_CHUNK; ++u) {
             const int K = min(K0 + u, ntk - 1);
-            a[u] = ws_load(W, ntk, I, K, lane);
-            b[u] = I == J ? a[u] : ws_load(W, ntk, J, K, lane);
+            a[u] = W.load(I, K, lane);
+            b[u] = I == J ? a[u] : W.load(J, K, lane);
         }
 #pragma unroll
         for (int u = 0; u < RIC_CHUNK; ++u)
@@ -169,9 +198,10 @@ __device__ __forceinline__ d4 potrf_terms(d4 acc, const MB_GLOBAL double *F, siz
 // ntk tile columns of C in the workspace (ntk = 0: F = chol(S)).  Only the
 // lower triangle of F is written, and at a failing pivot only the columns
 // before it.  Returns the LAPACK info (0, or the failing column + 1).
+template <class CS>
 __device__ __forceinline__ int syrk_potrf_wave(const MB_GLOBAL double *Sm, size_t lds, MB_GLOBAL double *F,
-                                               size_t ldf, int m, int nt, const MB_GLOBAL double *W,
-                                               int ntk, PotrfSmem &S, int lane)
+                                               size_t ldf, int m, int nt, const CS &W, int ntk,
+                                               PotrfSmem &S, int lane)
 {
     const int lr = lane & 15, lg = lane >> 4;
     if (lane == 0)
@@ -198,9 +228,13 @@ __device__ __forceinline__ int syrk_potrf_wave(const MB_GLOBAL double *Sm, size_
     return (S.fail == INT_MAX) ? 0 : S.fail + 1;
 }
 
+// LDS_TILES > 0: C lives in LDS (at most LDS_TILES tiles per wave); 0: in
+// the global workspace.
+template <int LDS_TILES>
 __global__ __launch_bounds__(RIC_WPB * 64) void riccati_kernel(RiccatiArgs p, int waves)
 {
     __shared__ PotrfSmem smem[RIC_WPB];
+    __shared__ double cbuf[RIC_WPB][LDS_TILES > 0 ? LDS_TILES * 256 : 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int w = blockIdx.x * RIC_WPB + wave;
@@ -209,12 +243,18 @@ __global__ __launch_bounds__(RIC_WPB * 64) void riccati_kernel(RiccatiArgs p, in
     PotrfSmem &S = smem[wave];
     const int nx = p.nx, nu = p.nu, N = p.N, m = nx + nu;
     const int ntm = (m + 15) / 16, ntx = (nx + 15) / 16;
-    MB_GLOBAL double *W = global_ptr(p.work) + (size_t)w * ((size_t)ntm * ntx * 256);
+    using CS = typename std::conditional<(LDS_TILES > 0), LdsC, GlobalC>::type;
+    CS W;
+    if constexpr (LDS_TILES > 0)
+        W = LdsC{cbuf[wave], ntx};
+    else
+        W = GlobalC{global_ptr(p.work) + (size_t)w * ((size_t)ntm * ntx * 256), ntx};
+    const GlobalC none{nullptr, 0};
     for (int64_t b = w; b < p.batch; b += waves) {
         MB_GLOBAL int *info = global_ptr(p.info) + b * (N + 1);
         const MB_GLOBAL double *QN = global_ptr(p.QN) + b * p.sQ;
         MB_GLOBAL double *LN = global_ptr(p.LN) + b * p.sL;
-        int st = syrk_potrf_wave(QN, (size_t)p.ldq, LN, (size_t)p.ldl, nx, ntx, W, 0, S, lane);
+        int st = syrk_potrf_wave(QN, (size_t)p.ldq, LN, (size_t)p.ldl, nx, ntx, none, 0, S, lane);
         if (lane == 0)
             info[N] = st;
         int n = N - 1;
@@ -327,14 +367,27 @@ int64_t riccati_slot_doubles(int nx, int nu)
     return ntm * ntx * 256;
 }
 
-hipError_t riccati_max_waves(int *waves)
+// C in LDS when its tiles fit this many per wave (12 KB: LDS then does not
+// lower the occupancy the kernel's registers allow)
+constexpr int RIC_LDS_TILES = 6;
+
+static bool riccati_lds(int nx, int nu)
+{
+    return ((nx + nu + 15) / 16) * ((nx + 15) / 16) <= RIC_LDS_TILES;
+}
+
+hipError_t riccati_max_waves(int nx, int nu, int *waves)
 {
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, riccati_kernel, RIC_WPB * 64, 0);
+        e = riccati_lds(nx, nu)
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &per_cu, riccati_kernel<RIC_LDS_TILES>, RIC_WPB * 64, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, riccati_kernel<0>,
+                                                               RIC_WPB * 64, 0);
     if (e != hipSuccess)
         return e;
     *waves = std::max(1, cus * std::max(per_cu, 1) * RIC_WPB);
@@ -350,7 +403,11 @@ hipError_t launch_riccati(const RiccatiArgs &a, int waves, hipStream_t s)
         return hipGetLastError();
     }
     const unsigned blocks = (unsigned)((waves + RIC_WPB - 1) / RIC_WPB);
-    hipLaunchKernelGGL(riccati_kernel, dim3(blocks), dim3(RIC_WPB * 64), 0, s, a, waves);
+    if (riccati_lds(a.nx, a.nu))
+        hipLaunchKernelGGL(riccati_kernel<RIC_LDS_TILES>, dim3(blocks), dim3(RIC_WPB * 64), 0, s, a,
+                           waves);
+    else
+        hipLaunchKernelGGL(riccati_kernel<0>, dim3(blocks), dim3(RIC_WPB * 64), 0, s, a, waves);
     return hipGetLastError();
 }
 
