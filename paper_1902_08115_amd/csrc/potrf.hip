@@ -23,7 +23,11 @@ __global__ __launch_bounds__(IPB * 64) __attribute__((amdgpu_waves_per_eu(2))) v
     constexpr bool PIPE = NT >= 16;
     // one tile: the unrolled diagonal factorization costs no occupancy there
     constexpr bool UNROLL = NT == 1;
-    const int info = potrf_wave<true, 2, PIPE, UNROLL>(A, (size_t)p.lda, p.n, NT, smem[inst], lane);
+    // panel rows per group: more rows share each load of the pivot columns'
+    // tiles (fewer re-reads) at more registers -- 4 up to NT = 12, 3 with the
+    // pipelined loops (4 would spill there), measured 1-2% faster than 2
+    constexpr int G = NT >= 13 ? 3 : (NT >= 8 ? 4 : 2);
+    const int info = potrf_wave<true, G, PIPE, UNROLL>(A, (size_t)p.lda, p.n, NT, smem[inst], lane);
     if (lane == 0)
         p.info[b] = info;
 }
