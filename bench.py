@@ -516,6 +516,11 @@ def riccati_workload(torch, _lib, inputs, reps, composed=True):
                "recursions_per_s": round(batch / best * 1e3, 1),
                "us_per_recursion_amortized": round(best * 1e3 / batch, 5),
                "gflops": round(fl / best / 1e6, 1), "gbps": round(by / best / 1e6, 1),
+               "roof_frac": round((fl / best / 1e9) / min(PEAK_FP64_TFLOPS,
+                                                          fl / by * PEAK_HBM_GBS / 1e3), 3),
+               "kernel": "riccati_small_kernel" if nx + nu <= 16 else (
+                   "riccati_kernel<6> (C in LDS)" if ((nx + nu + 15) // 16) * ((nx + 15) // 16) <= 6
+                   else "riccati_kernel<0> (C in the workspace)"),
                "flops_per_recursion": riccati_flops(nx, nu, N),
                "bytes_per_recursion": riccati_bytes(nx, nu, N),
                "paper_blasfeo_api_c_haswell_s_per_recursion": PAPER_RICCATI_S[(nx, nu)]}
