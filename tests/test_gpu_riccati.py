@@ -90,17 +90,18 @@ def test_riccati_vs_oracle(nx, nu, N, batch):
         _check_problem(Bh[b], Rh[b], Qh[b], nu, Fh[b], LNh[b], infoh[b], f"b={b}")
 
 
-def test_riccati_info_and_skipped_stages():
+@pytest.mark.parametrize("nx,nu", [(20, 7), (40, 20), (64, 32)])
+def test_riccati_info_and_skipped_stages(nx, nu):
     """A stage that is not positive definite at column j: info = j + 1 there
     (bit-exact against the oracle), -1 and untouched output for the stages
     after it in the recursion, the columns before j still factor values; a
-    non-SPD Q_N stops the whole recursion."""
+    non-SPD Q_N stops the whole recursion.  One shape per kernel family."""
     torch, _lib, blas = torch_mods()
-    nx, nu, N, batch = 20, 7, 6, 5
+    N, batch = 6, 5
     m = nx + nu
     say(f"riccati info nx={nx} nu={nu} N={N}")
-    BAt, RSQ, QN = _gen(nx, nu, N, batch, inputs.seed_for(41))
-    cases = {0: (3, 0), 1: (0, 22), 2: (5, 17), 4: (2, 16)}
+    BAt, RSQ, QN = _gen(nx, nu, N, batch, inputs.seed_for(41, nx))
+    cases = {0: (3, 0), 1: (0, m - 5), 2: (5, 17), 4: (2, 16)}
     for b, (stage, j) in cases.items():
         d = torch.arange(1.0, m + 1, dtype=torch.float64, device="cuda")
         d[j] = -1.0
