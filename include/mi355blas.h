@@ -155,6 +155,20 @@ int mb_dgemm_select(char transa, char transb, int m, int n, int k);
  * scalar alpha/beta quick returns are not considered. */
 const char *mb_dgemm_kernel_name(char transa, char transb, int m, int n, int k, int variant);
 
+/*
+ * Fortran-style aliases of mb_dgemm and mb_dpotrf (the dgemm_ calling form the
+ * paper writes out in Sec. 2.1): every scalar argument -- trans and uplo
+ * characters, sizes, leading dimensions, alpha, beta -- is passed by (host)
+ * pointer, in the same positions, and the work goes to the null stream.
+ * Matrices and info are device memory as in the plain calls.  A NULL scalar
+ * pointer is an illegal value of that argument; otherwise the status and
+ * semantics are those of mb_dgemm / mb_dpotrf.
+ */
+int mb_dgemm_(const char *transa, const char *transb, const int *m, const int *n, const int *k,
+              const double *alpha, const double *A, const int *lda, const double *B,
+              const int *ldb, const double *beta, double *C, const int *ldc);
+int mb_dpotrf_(const char *uplo, const int *n, double *A, const int *lda, int *info);
+
 /* --------------------------------------------------------------- dpotrf --- */
 
 /*

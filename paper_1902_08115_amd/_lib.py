@@ -33,6 +33,7 @@ EXPORTS = (
     "mb_dpotrf_l_backward_batched", "mb_dlaset_strided_batched", "mb_dlaset_batched",
     "mb_plan_create", "mb_plan_create_ex", "mb_plan_execute", "mb_plan_execute_mode", "mb_plan_stats",
     "mb_plan_destroy",
+    "mb_dgemm_", "mb_dpotrf_",
     "mb_dtrmm_rlnn_strided_batched", "mb_dsyrk_ln_strided_batched",
     "mb_riccati_strided_batched", "mb_riccati_workspace_size",
     "mb_status_string", "mb_version",
@@ -117,6 +118,10 @@ def _load():
     lib.mb_plan_execute_mode.argtypes = [vp, c_int, vp]
     lib.mb_plan_stats.argtypes = [vp, ctypes.POINTER(c_i64), c_int]
     lib.mb_plan_destroy.argtypes = [vp]
+    P = ctypes.POINTER
+    lib.mb_dgemm_.argtypes = [P(c_char), P(c_char), P(c_int), P(c_int), P(c_int), P(c_double), vp,
+                              P(c_int), vp, P(c_int), P(c_double), vp, P(c_int)]
+    lib.mb_dpotrf_.argtypes = [P(c_char), P(c_int), vp, P(c_int), vp]
     lib.mb_dtrmm_rlnn_strided_batched.argtypes = [c_int, c_int, c_double, vp, c_int, c_i64, vp,
                                                   c_int, c_i64, c_int, vp]
     lib.mb_dsyrk_ln_strided_batched.argtypes = [c_int, c_int, c_double, vp, c_int, c_i64, c_double,
@@ -236,6 +241,26 @@ def dlaset_strided_batched(uplo, m, n, alpha, beta, A, lda, sA, batch, stream=0)
 def dlaset_batched(uplo, m, n, alpha, beta, Aarr, lda, batch, stream=0) -> int:
     return lib.mb_dlaset_batched(_ch(uplo), m, n, float(alpha), float(beta), Aarr, lda, batch,
                                  stream)
+
+
+def dgemm_fortran(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc) -> int:
+    """mb_dgemm_: scalars by pointer (None passes a NULL pointer), null stream."""
+    def ref(ctype, v):
+        return None if v is None else ctypes.byref(ctype(v))
+    return lib.mb_dgemm_(ref(ctypes.c_char, _ch(transa) if transa is not None else None),
+                         ref(ctypes.c_char, _ch(transb) if transb is not None else None),
+                         ref(ctypes.c_int, m), ref(ctypes.c_int, n), ref(ctypes.c_int, k),
+                         ref(ctypes.c_double, alpha), A, ref(ctypes.c_int, lda), B,
+                         ref(ctypes.c_int, ldb), ref(ctypes.c_double, beta), C,
+                         ref(ctypes.c_int, ldc))
+
+
+def dpotrf_fortran(uplo, n, A, lda, info) -> int:
+    """mb_dpotrf_: scalars by pointer (None passes a NULL pointer), null stream."""
+    def ref(ctype, v):
+        return None if v is None else ctypes.byref(ctype(v))
+    return lib.mb_dpotrf_(ref(ctypes.c_char, _ch(uplo) if uplo is not None else None),
+                          ref(ctypes.c_int, n), A, ref(ctypes.c_int, lda), info)
 
 
 def dtrmm_rlnn_strided_batched(m, n, alpha, A, lda, sA, B, ldb, sB, batch, stream=0) -> int:

@@ -102,9 +102,22 @@ def dgemm_batched(transa, transb, m, n, k, alpha, Aptr, lda, Bptr, ldb, beta, Cp
     _raise("mb_dgemm_batched", st)
 
 
-def dpotrf(A, info=None, stream=None):
+def _check_info(info, stream):
+    """check=True: wait for the stream and raise on any non-zero info (the
+    behaviour of torch.linalg.cholesky_ex(check_errors=True))."""
+    (stream if stream is not None else torch.cuda.current_stream()).synchronize()
+    bad = torch.nonzero(info != 0)
+    if bad.numel():
+        b = int(bad[0, 0]) if bad.dim() > 1 else int(bad[0])
+        j = int(info.reshape(-1)[b])
+        raise torch.linalg.LinAlgError(
+            f"dpotrf: instance {b}: the leading minor of order {j} is not positive definite")
+
+
+def dpotrf(A, info=None, stream=None, check=False):
     """Lower Cholesky in place on a 2-D column-major tensor; returns the
-    device info tensor (shape (1,), int32) -- valid after the stream completes."""
+    device info tensor (shape (1,), int32) -- valid after the stream completes.
+    check=True synchronizes and raises torch.linalg.LinAlgError when info != 0."""
     lda, _ = _layout(A, "A", False)
     n = A.shape[0]
     if A.shape[1] != n:
@@ -113,10 +126,13 @@ def dpotrf(A, info=None, stream=None):
         info = torch.empty(1, dtype=torch.int32, device=A.device)
     st = _lib.dpotrf("L", n, A.data_ptr(), lda, info.data_ptr(), _stream(stream))
     _raise("mb_dpotrf", st)
+    if check:
+        _check_info(info, stream)
     return info
 
 
-def dpotrf_strided_batched(A, info=None, stream=None):
+def dpotrf_strided_batched(A, info=None, stream=None, check=False):
+    """Batched form of dpotrf over a 3-D column-major tensor (see dpotrf)."""
     lda, sA = _layout(A, "A", True)
     batch, n, n2 = A.shape
     if n != n2:
@@ -126,6 +142,8 @@ def dpotrf_strided_batched(A, info=None, stream=None):
     st = _lib.dpotrf_strided_batched("L", n, A.data_ptr(), lda, sA, info.data_ptr(), batch,
                                      _stream(stream))
     _raise("mb_dpotrf_strided_batched", st)
+    if check:
+        _check_info(info, stream)
     return info
 
 

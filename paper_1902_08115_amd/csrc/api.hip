@@ -559,6 +559,33 @@ int mb_dlaset_batched(char uplo, int m, int n, double alpha, double beta, double
     return to_status(mb::launch_laset(a, stream));
 }
 
+int mb_dgemm_(const char *transa, const char *transb, const int *m, const int *n, const int *k,
+              const double *alpha, const double *A, const int *lda, const double *B,
+              const int *ldb, const double *beta, double *C, const int *ldc)
+{
+    // every scalar is read through its pointer; a missing one is illegal
+    if (!transa) return -1;
+    if (!transb) return -2;
+    if (!m) return -3;
+    if (!n) return -4;
+    if (!k) return -5;
+    if (!alpha) return -6;
+    if (!lda) return -8;
+    if (!ldb) return -10;
+    if (!beta) return -11;
+    if (!ldc) return -13;
+    return mb_dgemm(*transa, *transb, *m, *n, *k, *alpha, A, *lda, B, *ldb, *beta, C, *ldc,
+                    nullptr);
+}
+
+int mb_dpotrf_(const char *uplo, const int *n, double *A, const int *lda, int *info)
+{
+    if (!uplo) return -1;
+    if (!n) return -2;
+    if (!lda) return -4;
+    return mb_dpotrf(*uplo, *n, A, *lda, info, nullptr);
+}
+
 int mb_dtrmm_rlnn_strided_batched(int m, int n, double alpha, const double *A, int lda,
                                   int64_t strideA, double *B, int ldb, int64_t strideB, int batch,
                                   hipStream_t stream)

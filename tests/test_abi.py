@@ -334,3 +334,26 @@ def test_trmm_syrk_argument_errors(L):
     assert s(6, 3, 0.0, None, 6, 18, 1.0, None, 6, 36, 2, None) == 0   # alpha 0, beta 1
     assert s(6, 0, 1.0, None, 6, 18, 1.0, None, 6, 36, 2, None) == 0   # k 0, beta 1
     assert s(0, 3, 1.0, None, 1, 0, 0.0, None, 1, 0, 2, None) == 0
+
+
+def test_fortran_style_aliases_arguments(L):
+    """mb_dgemm_ / mb_dpotrf_: a NULL scalar pointer is an illegal value of
+    that argument; other checks and quick returns are those of the plain calls."""
+    ok = ["N", "N", 4, 4, 4, 1.0, P, 4, P, 4, 1.0, P, 4]
+    for pos in (0, 1, 2, 3, 4, 5, 7, 9, 10, 12):
+        a = list(ok)
+        a[pos] = None
+        assert L.dgemm_fortran(*a) == -(pos + 1), pos
+    a = list(ok)
+    a[2] = -1
+    assert L.dgemm_fortran(*a) == -3
+    a = list(ok)
+    a[0] = "X"
+    assert L.dgemm_fortran(*a) == -1
+    assert L.dgemm_fortran("N", "N", 0, 4, 4, 1.0, None, 1, None, 4, 1.0, None, 1) == 0
+    assert L.dpotrf_fortran(None, 4, P, 4, P) == -1
+    assert L.dpotrf_fortran("L", None, P, 4, P) == -2
+    assert L.dpotrf_fortran("L", 4, P, None, P) == -4
+    assert L.dpotrf_fortran("L", -1, P, 4, P) == -2
+    assert L.dpotrf_fortran("L", 4, P, 3, P) == -4
+    assert L.dpotrf_fortran("U", 4, P, 4, P) == L.MB_ERR_UNSUPPORTED

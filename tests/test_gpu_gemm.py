@@ -296,3 +296,26 @@ def test_skinny_shapes(trans, variant):
 def _lib_name(ta, tb, m, n, k):
     from paper_1902_08115_amd import _lib
     return _lib.dgemm_kernel_name(ta, tb, m, n, k)
+
+
+def test_fortran_alias_matches_plain():
+    """mb_dgemm_ (scalars by pointer, null stream) matches mb_dgemm bit for bit
+    in every trans case."""
+    torch, _lib, _ = torch_mods()
+    g = inputs.rng(9100)
+    m, n, k = 23, 17, 29
+    for ta in "NT":
+        for tb in "NT":
+            (ar, ac), (br, bc) = gemm_dims(ta, tb, m, n, k)
+            A = inputs.colmajor(g, 1, ar, ac)
+            B = inputs.colmajor(g, 1, br, bc)
+            C = inputs.colmajor(g, 1, m, n)
+            say(f"dgemm fortran alias {ta}{tb}")
+            dA, dB = dev(A), dev(B)
+            c1, c2 = dev(C), dev(C)
+            assert _lib.dgemm(ta, tb, m, n, k, 0.5, dA.data_ptr(), ar, dB.data_ptr(), br, -1.5,
+                              c1.data_ptr(), m, 0) == 0
+            assert _lib.dgemm_fortran(ta, tb, m, n, k, 0.5, dA.data_ptr(), ar, dB.data_ptr(), br,
+                                      -1.5, c2.data_ptr(), m) == 0
+            torch.cuda.synchronize()
+            assert torch.equal(c1, c2), (ta, tb)

@@ -184,3 +184,32 @@ def test_full_batch_sampled():
             assert float(res) <= POTRF_TOL
         del A
         torch.cuda.empty_cache()
+
+
+def test_fortran_alias_and_check_option():
+    """mb_dpotrf_ (scalars by pointer, null stream) matches mb_dpotrf bit for
+    bit; blas.dpotrf(check=True) raises on a non-SPD matrix (as
+    torch.linalg.cholesky_ex with error checking does) and not on an SPD one."""
+    torch, _lib, blas = torch_mods()
+    n = 37
+    g = inputs.rng(8300)
+    A = inputs.spd_batch(g, 1, n)
+    say("dpotrf fortran alias / check option n=37")
+    d1, d2 = dev(A), dev(A)
+    i1 = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    i2 = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    assert _lib.dpotrf("L", n, d1.data_ptr(), n, i1.data_ptr(), 0) == 0
+    assert _lib.dpotrf_fortran("L", n, d2.data_ptr(), n, i2.data_ptr()) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(d1, d2) and int(i1[0]) == 0 and int(i2[0]) == 0
+    M = torch.from_numpy(A[0].T[:n, :n].copy()).cuda()
+    Mc = M.t().contiguous().t()
+    blas.dpotrf(Mc.clone().t().contiguous().t(), check=True)
+    bad = Mc.clone().t().contiguous().t()
+    bad[5, 5] = -1.0
+    with pytest.raises(torch.linalg.LinAlgError):
+        blas.dpotrf(bad, check=True)
+    batch = torch.stack([Mc, Mc]).transpose(1, 2).contiguous().transpose(1, 2)
+    batch[1, 3, 3] = -2.0
+    with pytest.raises(torch.linalg.LinAlgError):
+        blas.dpotrf_strided_batched(batch, check=True)
