@@ -185,6 +185,18 @@ def cpu_baseline(torch, oracle, gemm, potrf, flops_per_case):
         total_time += time.perf_counter() - t0
         total_flops += n ** 3 / 3.0 * cnt
         parts.append(f"dpotrf n={n}: {cnt} instances")
+    # one host thread on a smaller sample (1/16 of the flops per case)
+    one_flops, one_time = 0.0, 0.0
+    for (n, batch, A, B, C) in gemm:
+        cnt = int(max(1, min(batch, flops_per_case / 16 // (2 * n ** 3))))
+        a = A[:cnt].transpose(1, 2).contiguous().cpu().numpy().ravel()
+        b = B[:cnt].transpose(1, 2).contiguous().cpu().numpy().ravel()
+        c = C[:cnt].transpose(1, 2).contiguous().cpu().numpy().ravel()
+        t0 = time.perf_counter()
+        oracle.dgemm_strided_batched("N", "N", n, n, n, 1.0, a, n, n * n, b, n, n * n, 1.0, c, n,
+                                     n * n, cnt, nthreads=1)
+        one_time += time.perf_counter() - t0
+        one_flops += 2.0 * n ** 3 * cnt
     return {
         "value": total_flops / total_time / 1e9,
         "unit": "GFLOP/s",
@@ -193,7 +205,62 @@ def cpu_baseline(torch, oracle, gemm, potrf, flops_per_case):
         "seconds": round(total_time, 2),
         "sample": "leading instances of every sweep case, about "
                   f"{flops_per_case / 1e9:.1f} GFLOP per case: " + "; ".join(parts),
+        "value_1_thread": round(one_flops / one_time / 1e9, 3),
+        "sample_1_thread": "dgemm NN, leading instances of every sweep size, about "
+                           f"{flops_per_case / 16 / 1e9:.2f} GFLOP per size",
+        "cpu_model": host_cpu_model(),
     }
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def single_call(torch, _lib, oracle, inputs):
+    """The single plain call: dgemm NN, m = n = k = 32, lda = 32, alpha = beta =
+    1, U[-1,1) from the seed scheme; parity against the oracle and the call's
+    latency (HIP events around each call, median and min of 100)."""
+    n = 32
+    g = inputs.rng(inputs.seed_for(0, 0))
+    A = inputs.colmajor(g, 1, n, n)
+    B = inputs.colmajor(g, 1, n, n)
+    C = inputs.colmajor(g, 1, n, n)
+    dA, dB = (torch.from_numpy(X.ravel().copy()).cuda() for X in (A, B))
+    dC = torch.from_numpy(C.ravel().copy()).cuda()
+    st = _lib.dgemm("N", "N", n, n, n, 1.0, dA.data_ptr(), n, dB.data_ptr(), n, 1.0, dC.data_ptr(),
+                    n, torch.cuda.current_stream().cuda_stream)
+    assert st == 0, st
+    torch.cuda.synchronize()
+    ref = C.ravel().copy()
+    oracle.dgemm_raw("N", "N", n, n, n, 1.0, A.ravel().copy(), n, B.ravel().copy(), n, 1.0, ref, n)
+    got = dC.cpu().numpy()
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    work = torch.from_numpy(C.ravel().copy()).cuda()
+
+    def call():
+        _lib.dgemm("N", "N", n, n, n, 1.0, dA.data_ptr(), n, dB.data_ptr(), n, 1.0,
+                   work.data_ptr(), n, torch.cuda.current_stream().cuda_stream)
+    for _ in range(10):
+        call()
+    ts = []
+    for _ in range(100):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        call()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e3)
+    return {"m": n, "n": n, "k": n, "kernel": _lib.dgemm_kernel_name("N", "N", n, n, n),
+            "rel_err": err, "pass": err <= 1e-12, "latency_us_median": round(float(np.median(ts)), 2),
+            "latency_us_min": round(float(min(ts)), 2)}
 
 
 def parity_spot_check(torch, _lib, oracle, gemm, potrf, stream):
@@ -701,6 +768,8 @@ def main():
         per_size[f"dpotrf_n{n}"] = {
             "kernel": kname, "batch": batch, "ms": round(ms, 4),
             "gflops": round(fl / ms / 1e6, 1), "gbps": round(by / ms / 1e6, 1),
+            # LAPACK's exact count n^3/3 + n^2/2 + n/6 instead of the paper's n^3/3
+            "gflops_lapack_count": round((n ** 3 / 3 + n ** 2 / 2 + n / 6) * batch / ms / 1e6, 1),
             "roof_frac": round((fl / ms / 1e9) / min(PEAK_FP64_TFLOPS,
                                                       fl / by * PEAK_HBM_GBS / 1e3), 3)}
         c = classes.setdefault(kname, {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
@@ -740,10 +809,13 @@ def main():
                 "avg_launch_ms": d["avg_launch_ms"]}
 
     parity = None
+    single = None
     if not args.no_parity:
         import oracle
         log("parity spot check")
         parity = parity_spot_check(torch, _lib, oracle, gemm, potrf, stream)
+        single = single_call(torch, _lib, oracle, inputs)
+        log(f"single dgemm 32^3: {single['latency_us_median']} us median, err {single['rel_err']:.1e}")
 
     nxt = None
     if not args.no_next:
@@ -787,6 +859,7 @@ def main():
         "kernels": kernels,
         "per_size": per_size,
         "parity": parity,
+        "single_call": single,
         "next": nxt,
     }
     print(json.dumps(out), flush=True)
