@@ -310,7 +310,8 @@ def parity_spot_check(torch, _lib, oracle, gemm, potrf, stream):
 
 
 def crossover(torch, _lib, inputs, args):
-    """Direct vs packed dgemm at every sweep size and trans case."""
+    """The size switch measured: the direct, packed and register-tile kernel
+    families (and the automatic choice) at every sweep size and trans case."""
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
     rows = []
@@ -321,7 +322,7 @@ def crossover(torch, _lib, inputs, args):
         C = inputs.torch_colmajor(batch, n, n, seed=3)
         for trans in ("NN", "NT", "TN", "TT"):
             res = {}
-            for vname, v in (("direct", 1), ("packed", 2)):
+            for vname, v in (("direct", 1), ("packed", 2), ("regtile", 3), ("auto", 0)):
                 def call():
                     st = _lib.dgemm_strided_batched(trans[0], trans[1], n, n, n, 1.0,
                                                     A.data_ptr(), n, n * n, B.data_ptr(), n,
@@ -341,10 +342,11 @@ def crossover(torch, _lib, inputs, args):
                 fl, by = gemm_work(n, batch)
                 res[vname] = {"ms": ms, "gflops": fl / ms / 1e6, "gbps": by / ms / 1e6,
                               "kernel": _lib.dgemm_kernel_name(trans[0], trans[1], n, n, n, v)}
+            fam = {k: v for k, v in res.items() if k != "auto"}
             rows.append({"n": n, "trans": trans, "batch": batch, **res,
-                         "faster": min(res, key=lambda k: res[k]["ms"])})
-            log(f"crossover n={n} {trans}: direct {res['direct']['gflops']:.0f} GF/s, "
-                f"packed {res['packed']['gflops']:.0f} GF/s")
+                         "faster": min(fam, key=lambda k: fam[k]["ms"])})
+            log(f"crossover n={n} {trans}: " + ", ".join(
+                f"{k} {v['gflops']:.0f} GF/s" for k, v in res.items()))
         del A, B, C
         torch.cuda.empty_cache()
     print(json.dumps({"crossover": rows}))
