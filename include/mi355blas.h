@@ -445,7 +445,9 @@ int mb_dsyrk_ln_strided_batched(int n, int k, double alpha, const double *A, int
  * 2 KiB * ceil(m/16) * ceil(nx/16) and takes problems w, w + W, ...; W is the
  * smallest of batch, the slots that fit in work_bytes and the waves the
  * device holds at once.  mb_riccati_workspace_size gives the size for the
- * largest W (one slot is enough for a correct, slower run).  m <= 304
+ * largest W (one slot is enough for a correct, slower run).  Problems with
+ * m <= 16, or whose C has at most 6 tiles of 16 x 16, keep C on chip and do
+ * not touch the workspace (it is still validated).  m <= 304
  * (MB_ERR_UNSUPPORTED above).
  * Arguments: nx 1, nu 2, N 3, BAt 4, ldbat (>= max(1,m)) 5, stageBAt 6,
  * strideBAt 7, RSQ 8, ldrsq (>= max(1,m)) 9, stageRSQ 10, strideRSQ 11, QN 12,

@@ -14,10 +14,11 @@
 // R + C C^T is never written out.  Per stage:
 //   1. dtrmm: every 16 x 16 tile of C_n is a sum of MFMA tile products of
 //      BAt_n and the lower factor of the previous stage (read transposed
-//      through the cache; its upper triangle is masked, never read); the tile
-//      goes to the wave's workspace slot in a lane-private order (one
-//      coalesced 512-byte row per register), since C_n is needed in full
-//      while the factor is formed;
+//      through the cache; its upper triangle is masked, never read); C_n is
+//      needed in full while the factor is formed, so its tiles are kept in a
+//      lane-private order -- in the wave's part of LDS when they fit (at most
+//      six tiles), else in the wave's workspace slot (one coalesced 512-byte
+//      row per register);
 //   2. fused dsyrk + dpotrf by block column J: tile (I,J) of RSQ_n plus
 //      sum_K C(I,K) C(J,K)^T minus sum_{K<J} F(I,K) F(J,K)^T, then the
 //      diagonal tile factored in registers (factor_diag_tile) and the panel
