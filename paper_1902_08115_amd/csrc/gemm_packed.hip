@@ -26,8 +26,20 @@
 // barrier per k-panel suffices.  Each thread stages pairs of consecutive k of
 // one row and writes them with one 16-byte LDS store; operands contiguous
 // along k are also read with 16-byte global loads when every address is
-// 16-byte aligned (VEC = 2).  C is loaded before the k loop (beta != 0) so its
-// latency hides behind the products.
+// 16-byte aligned and k is even (VEC = 2).
+//   * Loads go through a raw buffer resource based at the panel's origin:
+//     an element outside the matrix gets an offset beyond the resource's
+//     record count, which the hardware answers with zero, so the staging code
+//     has no branches and the compiler interleaves the next panel's loads with
+//     the current panel's MFMAs (the order is pinned with scheduling-group
+//     hints).  Leading dimensions above 2^21 fall back to 64-bit addressing
+//     with clamped pointers (still branch-free).
+//   * While a wave issues its MFMAs it raises its wave priority, so that the
+//     waves sharing a SIMD take turns on the matrix core instead of all
+//     reaching their barrier at the same time.
+//   * C is loaded just before the last k-panel (beta != 0), so its registers
+//     are not live during the loop and four workgroups of the 64 x 64 tile fit
+//     on a CU.
 //
 // Launch shapes:
 //   * WAVE (IPB > 1): each wave owns one whole instance (C up to 16*TM x 16*TN),
@@ -38,6 +50,33 @@
 #include "mb_internal.h"
 
 namespace mb {
+
+// Raw buffer resource over a panel (record count just under 2 GiB); an offset
+// at or beyond kOob reads as zero without touching memory.
+constexpr unsigned kOob = 0x80000000u;
+// Largest leading dimension for 32-bit buffer offsets: 127 rows or columns of
+// a tile at that stride stay below the record count.
+constexpr int kBufMaxLd = 1 << 21;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const double *p)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(p), (short)0, 0x7ffffff0,
+                                             0x00020000);
+}
+__device__ __forceinline__ double buf_ld8(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ double2 buf_ld16(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+// 64-bit form: an invalid element reads the (valid) base address, then is zeroed.
+__device__ __forceinline__ double ptr_ld8(const double *base, const double *p, bool in)
+{
+    const double v = *(in ? p : base);
+    return in ? v : 0.0;
+}
 
 template <int WM_, int WN_, int TM_, int TN_, int IPB_, int BK_, int DB_>
 struct PackedCfg {
@@ -62,7 +101,7 @@ struct PackedCfg {
 //   !T: consecutive threads take consecutive rows, so each of the two 8-byte
 //       loads is coalesced across the wave;
 //   T:  consecutive threads take consecutive k pairs; one 16-byte load when
-//       VEC16 (every address 16-byte aligned), else two 8-byte loads.
+//       VEC16 (every address 16-byte aligned, k even), else two 8-byte loads.
 template <int ROWS, int NTHR, bool T, bool VEC16, int BK>
 struct Stage {
     static constexpr int PAIRS = ROWS * BK / 2;
@@ -81,30 +120,50 @@ struct Stage {
         }
     }
 
+    // global loads per thread and panel
+    static constexpr int LOADS = (T && VEC16) ? PER : 2 * PER;
+
+    // Stage the panel at k offset kb; rows r0.. of op(X) with nrows rows and
+    // k columns, zero outside.  BUF: 32-bit offsets into a buffer resource
+    // based at the panel's origin (ld <= kBufMaxLd); else clamped pointers.
+    template <bool BUF>
     __device__ __forceinline__ void load(const double *X, size_t ld, int nrows, int k, int r0,
                                          int kb, int tid)
     {
+        const double *base = T ? X + kb + (size_t)r0 * ld : X + r0 + (size_t)kb * ld;
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(base);
+        const unsigned ldb = (unsigned)ld * 8u;
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             int row, q;
             coords(tid + u * NTHR, row, q);
-            const int gr = r0 + row, gq = kb + q;
-            const bool rin = gr < nrows;
-            const bool in0 = rin && gq < k, in1 = rin && gq + 1 < k;
+            const bool rin = r0 + row < nrows;
+            const bool in0 = rin && kb + q < k, in1 = rin && kb + q + 1 < k;
             if (!T) {
-                const double *ptr = X + (size_t)gr + (size_t)gq * ld;
-                v[u][0] = in0 ? ptr[0] : 0.0;
-                v[u][1] = in1 ? ptr[ld] : 0.0;
-            } else {
-                const double *ptr = X + (size_t)gq + (size_t)gr * ld;
-                if (VEC16 && in1) {
-                    const double2 w = *reinterpret_cast<const double2 *>(ptr);
+                if (BUF) {
+                    const unsigned off = (unsigned)row * 8u + (unsigned)q * ldb;
+                    v[u][0] = buf_ld8(rs, in0 ? off : kOob);
+                    v[u][1] = buf_ld8(rs, in1 ? off + ldb : kOob);
+                } else {
+                    const double *ptr = base + row + (size_t)q * ld;
+                    v[u][0] = ptr_ld8(base, ptr, in0);
+                    v[u][1] = ptr_ld8(base, ptr + ld, in1);
+                }
+            } else if (BUF) {
+                const unsigned off = (unsigned)q * 8u + (unsigned)row * ldb;
+                if (VEC16) {
+                    // k is even on this path: a pair is either whole or outside
+                    const double2 w = buf_ld16(rs, in1 ? off : kOob);
                     v[u][0] = w.x;
                     v[u][1] = w.y;
                 } else {
-                    v[u][0] = in0 ? ptr[0] : 0.0;
-                    v[u][1] = in1 ? ptr[1] : 0.0;
+                    v[u][0] = buf_ld8(rs, in0 ? off : kOob);
+                    v[u][1] = buf_ld8(rs, in1 ? off + 8u : kOob);
                 }
+            } else {
+                const double *ptr = base + q + (size_t)row * ld;
+                v[u][0] = ptr_ld8(base, ptr, in0);
+                v[u][1] = ptr_ld8(base, ptr + 1, in1);
             }
         }
     }
@@ -121,11 +180,98 @@ struct Stage {
     }
 };
 
-template <bool TA, bool TB, class Cfg, int VEC>
+// Operands of one 16-deep step of a packed panel for this wave's tiles: lane
+// (lr, lg) takes k = kk + 4*lg .. +3 of row lr of each of its tiles.
+template <class Cfg>
+struct Frags {
+    double a[Cfg::TM][4], b[Cfg::TN][4];
+
+    __device__ __forceinline__ void read(const double *S, int kk, int wm, int wn, int lr, int lg)
+    {
+        constexpr int TM = Cfg::TM, TN = Cfg::TN, SK = Cfg::SK;
+        const double *As = S;
+        const double *Bs = S + Cfg::LDS_A;
+#pragma unroll
+        for (int ti = 0; ti < TM; ++ti) {
+            const double *src = &As[((wm * TM + ti) * 16 + lr) * SK + kk + 4 * lg];
+            const double2 x = *reinterpret_cast<const double2 *>(src);
+            const double2 y = *reinterpret_cast<const double2 *>(src + 2);
+            a[ti][0] = x.x;
+            a[ti][1] = x.y;
+            a[ti][2] = y.x;
+            a[ti][3] = y.y;
+        }
+#pragma unroll
+        for (int tj = 0; tj < TN; ++tj) {
+            const double *src = &Bs[((wn * TN + tj) * 16 + lr) * SK + kk + 4 * lg];
+            const double2 x = *reinterpret_cast<const double2 *>(src);
+            const double2 y = *reinterpret_cast<const double2 *>(src + 2);
+            b[tj][0] = x.x;
+            b[tj][1] = x.y;
+            b[tj][2] = y.x;
+            b[tj][3] = y.y;
+        }
+    }
+
+    __device__ __forceinline__ void mma(d4 (&acc)[Cfg::TM][Cfg::TN]) const
+    {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int ti = 0; ti < Cfg::TM; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < Cfg::TN; ++tj)
+                    acc[ti][tj] = mfma16(b[tj][s], a[ti][s], acc[ti][tj]);
+    }
+};
+
+// This wave's C tiles in accumulator order; zero outside the m x n window and
+// when beta == 0 (C is then not read).
+template <class Cfg, bool BUF>
+__device__ __forceinline__ void load_c(const double *C, size_t ldc, int m, int n, int i0, int j0,
+                                       int wm, int wn, int lr, int lg, double beta,
+                                       d4 (&cin)[Cfg::TM][Cfg::TN])
+{
+    const double *base = C + i0 + (size_t)j0 * ldc;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(base);
+    const unsigned ldb = (unsigned)ldc * 8u;
+#pragma unroll
+    for (int ti = 0; ti < Cfg::TM; ++ti) {
+        const int li = (wm * Cfg::TM + ti) * 16 + lr;
+#pragma unroll
+        for (int tj = 0; tj < Cfg::TN; ++tj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int lj = (wn * Cfg::TN + tj) * 16 + lg + 4 * r;
+                const bool in = beta != 0.0 && i0 + li < m && j0 + lj < n;
+                cin[ti][tj][r] = BUF ? buf_ld8(rs, in ? (unsigned)li * 8u + (unsigned)lj * ldb : kOob)
+                                     : ptr_ld8(base, base + li + (size_t)lj * ldc, in);
+            }
+    }
+}
+
+// Scheduling hints for the MFMA block of a staging panel: one global load and
+// a few address instructions after each of the first MFMAs, the rest of the
+// MFMAs after them.
+template <int NMFMA, int NLOAD>
+__device__ __forceinline__ void interleave_loads()
+{
+    constexpr int P = NLOAD < NMFMA ? NLOAD : NMFMA;
+#pragma unroll
+    for (int z = 0; z < P; ++z) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);  // VALU
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
+    }
+    if constexpr (NMFMA > P)
+        __builtin_amdgcn_sched_group_barrier(0x008, NMFMA - P, 0);
+}
+
+template <bool TA, bool TB, class Cfg, int VEC, bool BUF>
 __global__ __launch_bounds__(Cfg::NTHR *Cfg::IPB) void gemm_packed_kernel(GemmArgs p, int tiles_m,
                                                                           int tiles_n)
 {
-    constexpr int WM = Cfg::WM, WN = Cfg::WN, TM = Cfg::TM, TN = Cfg::TN, IPB = Cfg::IPB;
+    constexpr int WM = Cfg::WM, TM = Cfg::TM, TN = Cfg::TN, IPB = Cfg::IPB;
     constexpr int BK = Cfg::BK, DB = Cfg::DB;
     constexpr bool WAVE_ONLY = (IPB > 1);
     constexpr int SK = Cfg::SK;
@@ -171,81 +317,57 @@ __global__ __launch_bounds__(Cfg::NTHR *Cfg::IPB) void gemm_packed_kernel(GemmAr
         for (int tj = 0; tj < TN; ++tj)
             acc[ti][tj] = d4{0.0, 0.0, 0.0, 0.0};
 
-    // C is only needed by the epilogue: issue its loads first so that their
-    // latency hides behind the whole k loop.
-    const double alpha = p.alpha, beta = p.beta;
-    d4 cin[TM][TN];
-    if (beta != 0.0) {
-#pragma unroll
-        for (int ti = 0; ti < TM; ++ti) {
-            const int gi = i0 + (wm * TM + ti) * 16 + lr;
-#pragma unroll
-            for (int tj = 0; tj < TN; ++tj)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int gj = j0 + (wn * TN + tj) * 16 + lg + 4 * r;
-                    cin[ti][tj][r] = (gi < m && gj < n) ? C[(size_t)gi + (size_t)gj * ldc] : 0.0;
-                }
-        }
-    }
-
-    Stage<Cfg::BM, Cfg::NTHR, TA, VEC == 2, BK> sa;   // op(A): rows i; 'T' A is contiguous along k
-    Stage<Cfg::BN, Cfg::NTHR, !TB, VEC == 2, BK> sb;  // op(B)^T: rows j; 'N' B: contiguous along k
-    sa.load(A, lda, m, k, i0, 0, tid);
-    sb.load(B, ldb, n, k, j0, 0, tid);
+    using SA = Stage<Cfg::BM, Cfg::NTHR, TA, VEC == 2, BK>;   // op(A): rows i; 'T' A: k contiguous
+    using SB = Stage<Cfg::BN, Cfg::NTHR, !TB, VEC == 2, BK>;  // op(B)^T: rows j; 'N' B: k contiguous
+    SA sa;
+    SB sb;
+    sa.template load<BUF>(A, lda, m, k, i0, 0, tid);
+    sb.template load<BUF>(B, ldb, n, k, j0, 0, tid);
     sa.template store<SK>(&smem[grp][0][0], tid);
     sb.template store<SK>(&smem[grp][0][Cfg::LDS_A], tid);
     group_sync<WAVE_ONLY>();
 
+    // k loop: every panel but the last also stages the next one; the staging
+    // loads are issued among the first MFMAs of the panel's first 16 steps.
     int cur = 0;
-    for (int kb = 0; kb < k; kb += BK) {
-        const bool more = kb + BK < k;
-        if (more) {
-            sa.load(A, lda, m, k, i0, kb + BK, tid);
-            sb.load(B, ldb, n, k, j0, kb + BK, tid);
-        }
-        const double *As = &smem[grp][cur][0];
-        const double *Bs = &smem[grp][cur][Cfg::LDS_A];
+    const int klast = ((k - 1) / BK) * BK;
+    for (int kb = 0; kb < klast; kb += BK) {
+        const double *S = &smem[grp][cur][0];
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 16) {
-            double fa[TM][4], fb[TN][4];
-#pragma unroll
-            for (int ti = 0; ti < TM; ++ti) {
-                const double *src = &As[((wm * TM + ti) * 16 + lr) * SK + kk + 4 * lg];
-                const double2 x = *reinterpret_cast<const double2 *>(src);
-                const double2 y = *reinterpret_cast<const double2 *>(src + 2);
-                fa[ti][0] = x.x;
-                fa[ti][1] = x.y;
-                fa[ti][2] = y.x;
-                fa[ti][3] = y.y;
+            Frags<Cfg> f;
+            f.read(S, kk, wm, wn, lr, lg);
+            __builtin_amdgcn_s_setprio(1);
+            if (kk == 0) {
+                sa.template load<BUF>(A, lda, m, k, i0, kb + BK, tid);
+                sb.template load<BUF>(B, ldb, n, k, j0, kb + BK, tid);
+                f.mma(acc);
+                interleave_loads<4 * TM * TN, SA::LOADS + SB::LOADS>();
+            } else {
+                f.mma(acc);
             }
-#pragma unroll
-            for (int tj = 0; tj < TN; ++tj) {
-                const double *src = &Bs[((wn * TN + tj) * 16 + lr) * SK + kk + 4 * lg];
-                const double2 x = *reinterpret_cast<const double2 *>(src);
-                const double2 y = *reinterpret_cast<const double2 *>(src + 2);
-                fb[tj][0] = x.x;
-                fb[tj][1] = x.y;
-                fb[tj][2] = y.x;
-                fb[tj][3] = y.y;
-            }
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int ti = 0; ti < TM; ++ti)
-#pragma unroll
-                    for (int tj = 0; tj < TN; ++tj)
-                        acc[ti][tj] = mfma16(fb[tj][s], fa[ti][s], acc[ti][tj]);
+            __builtin_amdgcn_s_setprio(0);
         }
-        if (more) {
-            if constexpr (DB == 1)
-                group_sync<WAVE_ONLY>();  // everyone is done reading the single buffer
-            const int nxt = (DB == 2) ? (cur ^ 1) : 0;
-            sa.template store<SK>(&smem[grp][nxt][0], tid);
-            sb.template store<SK>(&smem[grp][nxt][Cfg::LDS_A], tid);
-            group_sync<WAVE_ONLY>();
-            cur = nxt;
-        }
+        const int nxt = (DB == 2) ? (cur ^ 1) : 0;
+        if constexpr (DB == 1)
+            group_sync<WAVE_ONLY>();  // everyone is done reading the single buffer
+        sa.template store<SK>(&smem[grp][nxt][0], tid);
+        sb.template store<SK>(&smem[grp][nxt][Cfg::LDS_A], tid);
+        group_sync<WAVE_ONLY>();
+        cur = nxt;
+    }
+
+    // C is needed only by the epilogue: its loads overlap the last panel.
+    const double alpha = p.alpha, beta = p.beta;
+    d4 cin[TM][TN];
+    load_c<Cfg, BUF>(C, ldc, m, n, i0, j0, wm, wn, lr, lg, beta, cin);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+        Frags<Cfg> f;
+        f.read(&smem[grp][cur][0], kk, wm, wn, lr, lg);
+        __builtin_amdgcn_s_setprio(1);
+        f.mma(acc);
+        __builtin_amdgcn_s_setprio(0);
     }
 
     // epilogue: C <= alpha*acc + beta*C, masked to the m x n window
@@ -295,17 +417,23 @@ constexpr int kPackedConfigs = 0 MB_PACKED_CONFIGS(MB_COUNT_CFG);
 
 // 16-byte global loads need every instance base, stride and leading dimension
 // of A and B to keep 16-byte alignment (pointer arrays are not inspected on
-// the host: they use 8-byte loads).
+// the host: they use 8-byte loads), and an even k (whole pairs).
 static bool vec2_ok(const GemmArgs &a)
 {
     if (a.Aarr || a.Barr)
         return false;
     const uintptr_t pa = (uintptr_t)a.A, pb = (uintptr_t)a.B;
     return (pa % 16 == 0) && (pb % 16 == 0) && (a.lda % 2 == 0) && (a.ldb % 2 == 0) &&
-           (a.sA % 2 == 0) && (a.sB % 2 == 0);
+           (a.sA % 2 == 0) && (a.sB % 2 == 0) && (a.k % 2 == 0);
 }
 
-template <bool TA, bool TB, class Cfg>
+// 32-bit buffer offsets cover every leading dimension up to kBufMaxLd.
+static bool buf_ok(const GemmArgs &a)
+{
+    return a.lda <= kBufMaxLd && a.ldb <= kBufMaxLd && a.ldc <= kBufMaxLd;
+}
+
+template <bool TA, bool TB, class Cfg, bool BUF = true>
 static hipError_t launch_cfg(const GemmArgs &a, hipStream_t s)
 {
     const bool v2 = vec2_ok(a);
@@ -324,17 +452,20 @@ static hipError_t launch_cfg(const GemmArgs &a, hipStream_t s)
         return hipErrorInvalidValue;
     const dim3 grid((unsigned)blocks), block(Cfg::NTHR * Cfg::IPB);
     if (v2)
-        hipLaunchKernelGGL((gemm_packed_kernel<TA, TB, Cfg, 2>), grid, block, 0, s, a, tiles_m,
-                           tiles_n);
+        hipLaunchKernelGGL((gemm_packed_kernel<TA, TB, Cfg, 2, BUF>), grid, block, 0, s, a,
+                           tiles_m, tiles_n);
     else
-        hipLaunchKernelGGL((gemm_packed_kernel<TA, TB, Cfg, 1>), grid, block, 0, s, a, tiles_m,
-                           tiles_n);
+        hipLaunchKernelGGL((gemm_packed_kernel<TA, TB, Cfg, 1, BUF>), grid, block, 0, s, a,
+                           tiles_m, tiles_n);
     return hipGetLastError();
 }
 
 template <bool TA, bool TB>
 static hipError_t launch_config_t(int config, const GemmArgs &a, hipStream_t s)
 {
+    // beyond 32-bit offsets: the 64 x 64 tile with 64-bit addressing
+    if (!buf_ok(a) && config >= 0 && config < kPackedConfigs)
+        return launch_cfg<TA, TB, PackedCfg<2, 2, 2, 2, 1, 16, 1>, false>(a, s);
     switch (config) {
 #define MB_CASE_CFG(id, name, wm, wn, tm, tn, ipb, bk, db)                                     \
     case id:                                                                                \

@@ -266,6 +266,36 @@ def test_every_packed_config_exact():
                                              0.0, 16, 17, 289, 1, 0, s) == _lib.MB_ERR_UNSUPPORTED
 
 
+@pytest.mark.parametrize("trans", ["NN", "TT"])
+def test_packed_huge_leading_dimension(trans):
+    """A leading dimension above 2^21 is beyond the packed kernel's 32-bit
+    buffer offsets: the launcher falls back to 64-bit addressing.  A alone
+    has the huge stride (about 1.2 GB on the device); bit-exact on integer
+    data against the oracle on the compact operands."""
+    torch, _lib, _ = torch_mods()
+    s = torch.cuda.current_stream().cuda_stream
+    ta, tb = trans
+    m, n, k = 70, 37, 45
+    g = inputs.rng(7600 + TRANS.index(trans))
+    A, B, C = _make(g, ta, tb, m, n, k, 1, integer=True)
+    ar, ac = A.shape[2], A.shape[1]
+    lda = (1 << 21) + 8
+    big = torch.full((ac, lda), float("nan"), dtype=torch.float64, device="cuda")
+    big[:, :ar] = torch.from_numpy(A[0]).cuda()
+    dB, dC = dev(B), dev(C)
+    say(f"dgemm huge lda={lda} {trans} {m}x{n}x{k}")
+    st = _lib.dgemm_strided_batched_config(ta, tb, m, n, k, 1.0, big.data_ptr(), lda, ac * lda,
+                                           dB.data_ptr(), B.shape[2], B.shape[1] * B.shape[2],
+                                           -0.5, dC.data_ptr(), C.shape[2],
+                                           C.shape[1] * C.shape[2], 1, 5, s)
+    assert st == 0, st
+    Cg = host(dC).reshape(C.shape)
+    Cr = oracle_gemm_batch(ta, tb, m, n, k, 1.0, A, ar, B, B.shape[2], -0.5, C, C.shape[2], 1)
+    assert np.array_equal(Cg, Cr, equal_nan=True)
+    del big
+    torch.cuda.empty_cache()
+
+
 SKINNY = [(4, 4, 1), (4, 4, 2), (4, 4, 3), (4, 4, 17), (4, 4, 300), (1, 300, 5), (4, 300, 300),
           (4, 37, 200), (16, 17, 33), (300, 4, 300), (97, 4, 15), (17, 16, 9), (3, 5, 300),
           (16, 16, 257), (33, 2, 64)]
