@@ -15,17 +15,17 @@
 
 namespace mb {
 
-constexpr double kFusedGemmFixedNs = 3582.3;
-constexpr double kFusedGemmTileNs = 759.8;
-constexpr double kFusedGemmMfmaNs = 320.2;
-constexpr double kFusedGemmLoadNs = 649.3;
-constexpr double kFusedPotrfNs[4] = {2874.5, 13981.2, -1322.2, 273.4};
-constexpr double kFusedAdjointNs[4] = {-2548.8, 68865.4, -17597.5, 3372.1};
+constexpr double kFusedGemmFixedNs = 3691.9;
+constexpr double kFusedGemmTileNs = 676.5;
+constexpr double kFusedGemmMfmaNs = 336.1;
+constexpr double kFusedGemmLoadNs = 634.8;
+constexpr double kFusedPotrfNs[4] = {4616.6, 11500.8, -1022.2, 247.7};
+constexpr double kFusedAdjointNs[4] = {-19212.6, 56025.4, -13507.1, 3107.5};
 constexpr double kFusedLasetNs = 2000.0;
 constexpr int kFusedTwoMin = 16;
 // waves of a 4-wave workgroup that start on the dpotrf class:
 // round(4 * min(1, share * kFusedPotrfShareScale)), share = that class's
 // estimated fraction of the work (measured best split on the uneven batch)
-constexpr double kFusedPotrfShareScale = 1.721;
+constexpr double kFusedPotrfShareScale = 1.802;
 
 }  // namespace mb
