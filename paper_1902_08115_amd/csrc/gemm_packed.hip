@@ -181,47 +181,76 @@ struct Stage {
 };
 
 // Operands of one 16-deep step of a packed panel for this wave's tiles: lane
-// (lr, lg) takes k = kk + 4*lg .. +3 of row lr of each of its tiles.
+// (lr, lg) takes k = kk + 4*lg .. +3 of row lr of each of its tiles.  Waves
+// with eight or more MFMA tiles read and multiply them in two halves of two k
+// (one 16-byte LDS read per tile and half), which keeps half the operand
+// registers live -- three waves per SIMD instead of two; smaller waves read
+// all four k at once (measured faster there: fewer waits on LDS).
 template <class Cfg>
 struct Frags {
-    double a[Cfg::TM][4], b[Cfg::TN][4];
+    static constexpr int TM = Cfg::TM, TN = Cfg::TN, SK = Cfg::SK;
+    static constexpr bool HALF = TM * TN >= 8;
+    const double *As, *Bs;
+    double a[HALF ? 1 : TM][4], b[HALF ? 1 : TN][4];
 
     __device__ __forceinline__ void read(const double *S, int kk, int wm, int wn, int lr, int lg)
     {
-        constexpr int TM = Cfg::TM, TN = Cfg::TN, SK = Cfg::SK;
-        const double *As = S;
-        const double *Bs = S + Cfg::LDS_A;
+        As = &S[(wm * TM * 16 + lr) * SK + kk + 4 * lg];
+        Bs = &S[Cfg::LDS_A + (wn * TN * 16 + lr) * SK + kk + 4 * lg];
+        if constexpr (!HALF) {
 #pragma unroll
-        for (int ti = 0; ti < TM; ++ti) {
-            const double *src = &As[((wm * TM + ti) * 16 + lr) * SK + kk + 4 * lg];
-            const double2 x = *reinterpret_cast<const double2 *>(src);
-            const double2 y = *reinterpret_cast<const double2 *>(src + 2);
-            a[ti][0] = x.x;
-            a[ti][1] = x.y;
-            a[ti][2] = y.x;
-            a[ti][3] = y.y;
-        }
+            for (int ti = 0; ti < TM; ++ti) {
+                const double2 x = *reinterpret_cast<const double2 *>(As + ti * 16 * SK);
+                const double2 y = *reinterpret_cast<const double2 *>(As + ti * 16 * SK + 2);
+                a[ti][0] = x.x;
+                a[ti][1] = x.y;
+                a[ti][2] = y.x;
+                a[ti][3] = y.y;
+            }
 #pragma unroll
-        for (int tj = 0; tj < TN; ++tj) {
-            const double *src = &Bs[((wn * TN + tj) * 16 + lr) * SK + kk + 4 * lg];
-            const double2 x = *reinterpret_cast<const double2 *>(src);
-            const double2 y = *reinterpret_cast<const double2 *>(src + 2);
-            b[tj][0] = x.x;
-            b[tj][1] = x.y;
-            b[tj][2] = y.x;
-            b[tj][3] = y.y;
+            for (int tj = 0; tj < TN; ++tj) {
+                const double2 x = *reinterpret_cast<const double2 *>(Bs + tj * 16 * SK);
+                const double2 y = *reinterpret_cast<const double2 *>(Bs + tj * 16 * SK + 2);
+                b[tj][0] = x.x;
+                b[tj][1] = x.y;
+                b[tj][2] = y.x;
+                b[tj][3] = y.y;
+            }
         }
     }
 
-    __device__ __forceinline__ void mma(d4 (&acc)[Cfg::TM][Cfg::TN]) const
+    __device__ __forceinline__ void mma(d4 (&acc)[TM][TN]) const
     {
+        if constexpr (!HALF) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+            for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int ti = 0; ti < Cfg::TM; ++ti)
+                for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
-                for (int tj = 0; tj < Cfg::TN; ++tj)
-                    acc[ti][tj] = mfma16(b[tj][s], a[ti][s], acc[ti][tj]);
+                    for (int tj = 0; tj < TN; ++tj)
+                        acc[ti][tj] = mfma16(b[tj][s], a[ti][s], acc[ti][tj]);
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                double2 x[TM], y[TN];
+#pragma unroll
+                for (int ti = 0; ti < TM; ++ti)
+                    x[ti] = *reinterpret_cast<const double2 *>(As + ti * 16 * SK + 2 * h);
+#pragma unroll
+                for (int tj = 0; tj < TN; ++tj)
+                    y[tj] = *reinterpret_cast<const double2 *>(Bs + tj * 16 * SK + 2 * h);
+#pragma unroll
+                for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < TN; ++tj)
+                        acc[ti][tj] = mfma16(y[tj].x, x[ti].x, acc[ti][tj]);
+#pragma unroll
+                for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < TN; ++tj)
+                        acc[ti][tj] = mfma16(y[tj].y, x[ti].y, acc[ti][tj]);
+            }
+        }
     }
 };
 
@@ -410,7 +439,11 @@ __global__ __launch_bounds__(Cfg::NTHR *Cfg::IPB) void gemm_packed_kernel(GemmAr
     X(11, "tile96_k32", 2, 2, 3, 3, 1, 32, 1)                                                 \
     X(12, "tile128_w8_k32", 2, 4, 4, 2, 1, 32, 1)                                            \
     X(13, "tile64x128_w8_k32", 2, 4, 2, 2, 1, 32, 1)                                         \
-    X(14, "tile128_w4_k32", 2, 2, 4, 4, 1, 32, 1)
+    X(14, "tile128_w4_k32", 2, 2, 4, 4, 1, 32, 1)                                            \
+    X(15, "tile128x64_w4", 2, 2, 4, 2, 1, 16, 1)                                             \
+    X(16, "tile128x64_w4_db", 2, 2, 4, 2, 1, 16, 2)                                          \
+    X(17, "tile64x128_w4", 2, 2, 2, 4, 1, 16, 1)                                             \
+    X(18, "tile64x128_w8_db", 2, 4, 2, 2, 1, 16, 2)
 
 #define MB_COUNT_CFG(id, name, wm, wn, tm, tn, ipb, bk, db) +1
 constexpr int kPackedConfigs = 0 MB_PACKED_CONFIGS(MB_COUNT_CFG);

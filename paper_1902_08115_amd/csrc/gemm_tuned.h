@@ -19,19 +19,19 @@ constexpr int kGemmTuneEntries = 14;
 constexpr int kGemmTuneMaxDim[kGemmTuneEntries] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 320, 1 << 30};
 // {variant, packed configuration} per trans case and size class
 constexpr int kGemmTune[4][kGemmTuneEntries][2] = {
-    {{3, -1}, {3, -1}, {3, -1}, {3, -1}, {3, -1}, {3, -1}, {2, 3}, {3, -1}, {2, 6}, {2, 13}, {2, 11}, {2, 13}, {2, 5}, {2, 5}},
-    {{3, -1}, {3, -1}, {3, -1}, {3, -1}, {3, -1}, {2, 1}, {2, 2}, {3, -1}, {2, 6}, {2, 13}, {2, 6}, {2, 13}, {2, 5}, {2, 5}},
-    {{2, 1}, {2, 1}, {2, 1}, {2, 1}, {2, 1}, {3, -1}, {2, 3}, {2, 4}, {2, 6}, {2, 13}, {2, 3}, {2, 13}, {2, 5}, {2, 5}},
-    {{2, 1}, {2, 1}, {2, 1}, {2, 1}, {2, 1}, {2, 1}, {2, 3}, {2, 4}, {2, 6}, {2, 13}, {2, 5}, {2, 13}, {2, 5}, {2, 5}},
+    {{3, -1}, {3, -1}, {3, -1}, {3, -1}, {3, -1}, {3, -1}, {2, 3}, {3, -1}, {2, 11}, {2, 13}, {2, 5}, {2, 15}, {2, 5}, {2, 5}},
+    {{3, -1}, {3, -1}, {3, -1}, {3, -1}, {3, -1}, {2, 1}, {2, 3}, {3, -1}, {2, 6}, {2, 15}, {2, 5}, {2, 15}, {2, 5}, {2, 5}},
+    {{2, 1}, {2, 1}, {2, 1}, {2, 1}, {2, 1}, {2, 2}, {2, 3}, {2, 5}, {2, 11}, {2, 3}, {2, 3}, {2, 15}, {2, 5}, {2, 5}},
+    {{2, 1}, {2, 1}, {2, 1}, {2, 1}, {2, 1}, {2, 1}, {2, 3}, {2, 4}, {2, 6}, {2, 15}, {2, 5}, {2, 15}, {2, 5}, {2, 5}},
 };
 
 // {variant, packed configuration} per skinny class, trans case and size class
 constexpr int kGemmSkinny[3][4][kGemmTuneEntries][2] = {
     {
-        {{1, -1}, {3, -1}, {2, 0}, {2, 0}, {3, -1}, {2, 0}, {2, 0}, {3, -1}, {3, -1}, {3, -1}, {2, 0}, {2, 0}, {3, -1}, {3, -1}},
+        {{1, -1}, {2, 0}, {2, 0}, {2, 0}, {3, -1}, {2, 0}, {2, 0}, {2, 0}, {2, 0}, {2, 0}, {2, 0}, {2, 0}, {3, -1}, {3, -1}},
         {{1, -1}, {1, -1}, {2, 0}, {2, 0}, {1, -1}, {1, -1}, {1, -1}, {1, -1}, {1, -1}, {1, -1}, {3, -1}, {3, -1}, {3, -1}, {3, -1}},
-        {{1, -1}, {2, 0}, {2, 0}, {2, 0}, {3, -1}, {2, 0}, {2, 0}, {3, -1}, {3, -1}, {3, -1}, {2, 0}, {2, 0}, {3, -1}, {3, -1}},
-        {{1, -1}, {2, 0}, {2, 0}, {2, 0}, {3, -1}, {2, 0}, {2, 0}, {2, 0}, {3, -1}, {2, 0}, {3, -1}, {2, 0}, {3, -1}, {3, -1}},
+        {{1, -1}, {2, 0}, {2, 0}, {2, 0}, {2, 0}, {2, 0}, {2, 0}, {2, 0}, {2, 0}, {2, 0}, {2, 0}, {2, 0}, {3, -1}, {3, -1}},
+        {{1, -1}, {2, 0}, {2, 0}, {2, 0}, {3, -1}, {2, 0}, {2, 0}, {2, 0}, {2, 0}, {2, 0}, {2, 0}, {2, 0}, {3, -1}, {3, -1}},
     },
     {
         {{3, -1}, {3, -1}, {3, -1}, {3, -1}, {3, -1}, {3, -1}, {3, -1}, {3, -1}, {3, -1}, {3, -1}, {3, -1}, {3, -1}, {3, -1}, {3, -1}},
