@@ -472,6 +472,22 @@ int mb_riccati_strided_batched(int nx, int nu, int N, const double *BAt, int ldb
  */
 int mb_riccati_workspace_size(int nx, int nu, int batch, size_t *bytes);
 
+/* ---------------------------------------------------------- ceilings --- */
+
+/*
+ * Measured FP64 compute ceilings (roofline support; not part of the BLAS
+ * path).  Launches a register-only loop on `stream`: kind 0 = FP64 matrix
+ * cores (v_mfma_f64_16x16x4, four independent chains per wave), kind 1 =
+ * FP64 vector FMA (eight chains per lane); `blocks` workgroups of 256 threads
+ * each run `iters` iterations and store one double per thread to `out`
+ * (device, blocks * 256 doubles, caller-owned).  *flops (host) receives the
+ * exact flop count of the launch; the caller times it (events on `stream`).
+ * Arguments: kind 1, blocks 2, iters 3, out 4, flops 5 (illegal -> -position);
+ * MB_ERR_HIP on a launch failure.
+ */
+int mb_ceiling_fp64(int kind, int blocks, int iters, double *out, double *flops,
+                    hipStream_t stream);
+
 /* ---------------------------------------------------------------- misc --- */
 
 /* Static text for a status code (never NULL). */

@@ -36,6 +36,7 @@ EXPORTS = (
     "mb_dgemm_", "mb_dpotrf_",
     "mb_dtrmm_rlnn_strided_batched", "mb_dsyrk_ln_strided_batched",
     "mb_riccati_strided_batched", "mb_riccati_workspace_size",
+    "mb_ceiling_fp64",
     "mb_status_string", "mb_version",
 )
 
@@ -102,6 +103,7 @@ def _load():
     lib.mb_dgemm_kernel_name.argtypes = [c_char, c_char, c_int, c_int, c_int, c_int]
     lib.mb_dpotrf_kernel_name.argtypes = [c_int]
     lib.mb_version.argtypes = []
+    lib.mb_ceiling_fp64.argtypes = [c_int, c_int, c_int, vp, vp, vp]
     lib.mb_dgemm_backward_strided_batched.argtypes = [
         c_char, c_char, c_int, c_int, c_int, c_double, vp, c_int, c_i64, vp, c_int, c_i64,
         vp, c_int, c_i64, vp, c_int, c_i64, vp, c_int, c_i64, c_int, vp]
@@ -290,6 +292,13 @@ def riccati_workspace_size(nx, nu, batch):
 
 def version() -> int:
     return lib.mb_version()
+
+
+def ceiling_fp64(kind, blocks, iters, out, stream=0):
+    """(status, flops) of one launch of mb_ceiling_fp64 (kind 0 MFMA, 1 FMA)."""
+    fl = ctypes.c_double(0.0)
+    st = lib.mb_ceiling_fp64(kind, blocks, iters, out, ctypes.byref(fl), stream)
+    return st, fl.value
 
 
 def problems_array(problems):

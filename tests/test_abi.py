@@ -357,3 +357,15 @@ def test_fortran_style_aliases_arguments(L):
     assert L.dpotrf_fortran("L", -1, P, 4, P) == -2
     assert L.dpotrf_fortran("L", 4, P, 3, P) == -4
     assert L.dpotrf_fortran("U", 4, P, 4, P) == L.MB_ERR_UNSUPPORTED
+
+
+def test_ceiling_probe_argument_errors(L):
+    """mb_ceiling_fp64 validates every argument (its position) before launching."""
+    import ctypes
+    fl = ctypes.c_double(0.0)
+    buf = ctypes.c_void_p(16)  # never dereferenced: every call below fails its checks first
+    assert L.lib.mb_ceiling_fp64(2, 1, 1, buf, ctypes.byref(fl), None) == -1
+    assert L.lib.mb_ceiling_fp64(0, 0, 1, buf, ctypes.byref(fl), None) == -2
+    assert L.lib.mb_ceiling_fp64(1, 1, 0, buf, ctypes.byref(fl), None) == -3
+    assert L.lib.mb_ceiling_fp64(0, 1, 1, None, ctypes.byref(fl), None) == -4
+    assert L.lib.mb_ceiling_fp64(0, 1, 1, buf, None, None) == -5
