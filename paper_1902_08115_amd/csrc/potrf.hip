@@ -27,7 +27,12 @@ __global__ __launch_bounds__(IPB * 64) __attribute__((amdgpu_waves_per_eu(2))) v
     // tiles (fewer re-reads) at more registers -- 4 up to NT = 12, 3 with the
     // pipelined loops (4 would spill there), measured 1-2% faster than 2
     constexpr int G = NT >= 13 ? 3 : (NT >= 8 ? 4 : 2);
-    const int info = potrf_wave<true, G, PIPE, UNROLL>(A, (size_t)p.lda, p.n, NT, smem[inst], lane);
+    // first panel rows updated inside the diagonal-block loop (they share its
+    // pivot tiles): three rows with the pipelined loops (4.8% faster at
+    // n = 256), two where three would spill (NT = 17, 19); the plain-loop
+    // orders keep none -- there the extra registers cost a wave per SIMD
+    constexpr int G1 = PIPE ? ((NT == 17 || NT == 19) ? 2 : 3) : 0;
+    const int info = potrf_wave<true, G, PIPE, UNROLL, G1>(A, (size_t)p.lda, p.n, NT, smem[inst], lane);
     if (lane == 0)
         p.info[b] = info;
 }

@@ -15,8 +15,9 @@
 // matrix-core work).  Tiles are held in accumulator order -- lane (g, i),
 // register r holds element (16I + i, 16J + g + 4r).  With PAIR, block columns
 // are processed two at a time, so every factored tile loaded for the update
-// serves both (half the re-reads of the factor, more registers).  For one
-// block column J:
+// serves both (half the re-reads of the factor, more registers); with G1 the
+// first G1 panel rows are updated in the diagonal block's loop, which loads
+// the pivot tiles L(J,K), L(J1,K) they need anyway.  For one block column J:
 //   1. tile(J,J) of A minus L(J,K) * L(J,K)^T for every factored block column
 //      K < J: four MFMA steps per K whose operands are the registers s of
 //      L(J,K) loaded from the factor already written (the k index of step s in
@@ -224,7 +225,7 @@ __device__ __forceinline__ d4 update_nt(d4 acc, const d4 &x, const d4 &y)
 // Factor the n x n lower triangle of A (nt = ceil(n / 16) tiles) with the
 // calling wave; returns the LAPACK info (0, or the failing column + 1).  S is
 // this wave's private LDS block.
-template <bool PAIR, int G = 2, bool PIPE = true, bool UNROLL = false>
+template <bool PAIR, int G = 2, bool PIPE = true, bool UNROLL = false, int G1 = 0>
 __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT, PotrfSmem &S,
                                           int lane)
 {
@@ -255,28 +256,78 @@ __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT
         // which stands in for J1 when there is no second column.
         // (PIPE = false keeps the plain loops, which need fewer registers.)
         const int R1 = two ? J1 : NT;
+        // With G1 > 0 the first G1 panel rows below the pair are updated in
+        // the same loop: they need exactly the pivot tiles L(J,K), L(J1,K)
+        // that the diagonal block loads, so those are read once per pair
+        // instead of once more for the first panel group.
+        constexpr int NF = G1 > 0 ? G1 : 1;
+        const int F0 = J + STEP;
+        d4 f0[NF], f1[NF];
+#pragma unroll
+        for (int g = 0; g < NF; ++g) {
+            const bool in = G1 > 0 && F0 + g < NT;
+            f0[g] = in ? load_tile(A, lda, n, F0 + g, J, lr, lg, false) : d4{0.0, 0.0, 0.0, 0.0};
+            f1[g] = (in && two) ? load_tile(A, lda, n, F0 + g, J1, lr, lg, false)
+                                : d4{0.0, 0.0, 0.0, 0.0};
+        }
         if (!PIPE) {
             for (int K = 0; K < J; ++K) {
                 const d4 l0 = load_tile(A, lda, n, J, K, lr, lg, false);
                 t00 = update_nt(t00, l0, l0);
+                d4 l1 = d4{0.0, 0.0, 0.0, 0.0};
                 if (two) {
-                    const d4 l1 = load_tile(A, lda, n, J1, K, lr, lg, false);
+                    l1 = load_tile(A, lda, n, J1, K, lr, lg, false);
                     t10 = update_nt(t10, l1, l0);
                     t11 = update_nt(t11, l1, l1);
                 }
+                if constexpr (G1 > 0) {
+#pragma unroll
+                    for (int g = 0; g < NF; ++g) {
+                        if (F0 + g < NT) {
+                            const d4 lf = load_tile(A, lda, n, F0 + g, K, lr, lg, false);
+                            f0[g] = update_nt(f0[g], lf, l0);
+                            if (two)
+                                f1[g] = update_nt(f1[g], lf, l1);
+                        }
+                    }
+                }
             }
-        } else if (J > 0) {
+        }
+        if (PIPE && J > 0) {
             d4 p0 = load_tile(A, lda, n, J, 0, lr, lg, false);
             d4 p1 = load_tile(A, lda, n, R1, 0, lr, lg, false);
+            d4 pf[NF];
+#pragma unroll
+            for (int g = 0; g < NF; ++g)
+                pf[g] = G1 > 0 ? load_tile(A, lda, n, F0 + g, 0, lr, lg, false) : d4{0.0, 0.0, 0.0, 0.0};
             for (int K = 0; K < J; ++K) {
                 const d4 l0 = p0, l1 = p1;
+                d4 lf[NF];
+#pragma unroll
+                for (int g = 0; g < NF; ++g)
+                    lf[g] = pf[g];
                 const int Kn = min(K + 1, J - 1);
                 p0 = load_tile(A, lda, n, J, Kn, lr, lg, false);
                 p1 = load_tile(A, lda, n, R1, Kn, lr, lg, false);
+                if constexpr (G1 > 0) {
+#pragma unroll
+                    for (int g = 0; g < NF; ++g)
+                        pf[g] = load_tile(A, lda, n, F0 + g, Kn, lr, lg, false);
+                }
                 t00 = update_nt(t00, l0, l0);
                 if (two) {
                     t10 = update_nt(t10, l1, l0);
                     t11 = update_nt(t11, l1, l1);
+                }
+                if constexpr (G1 > 0) {
+#pragma unroll
+                    for (int g = 0; g < NF; ++g) {
+                        if (F0 + g < NT) {
+                            f0[g] = update_nt(f0[g], lf[g], l0);
+                            if (two)
+                                f1[g] = update_nt(f1[g], lf[g], l1);
+                        }
+                    }
                 }
             }
         }
@@ -297,8 +348,21 @@ __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT
                 store_diag(A, lda, n, J1, t11, fail_col, lr, lg);
             }
         }
-        // --- panel rows I > J1, G at a time, both columns ---
-        for (int I0 = J + STEP; I0 < NT; I0 += G) {
+        if constexpr (G1 > 0) {
+#pragma unroll
+            for (int g = 0; g < NF; ++g) {
+                if (F0 + g < NT) {
+                    const d4 x0 = solve_right(f0[g], w0);
+                    store_tile(A, lda, n, F0 + g, J, x0, fail_col, lr, lg);
+                    if (two) {
+                        const d4 x1 = solve_right(update_nt(f1[g], x0, l10), w1);
+                        store_tile(A, lda, n, F0 + g, J1, x1, fail_col, lr, lg);
+                    }
+                }
+            }
+        }
+        // --- panel rows I > J1 (after the first G1), G at a time, both columns ---
+        for (int I0 = J + STEP + G1; I0 < NT; I0 += G) {
             d4 a0[G], a1[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
