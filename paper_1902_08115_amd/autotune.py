@@ -11,7 +11,9 @@ resident in device memory), and writes
 
 This is the paper's variant switching (Sec. 2.4: the switching point is found
 by measurement and differs per routine and architecture) applied to the
-kernel menu of this library.  Needs a GPU:
+kernel menu of this library.  A class keeps the choice of the committed
+gemm_tuned.h while that choice is within --keep-within (2%) of the fastest
+candidate, so repeated runs do not reshuffle near-ties.  Needs a GPU:
 
   python -m paper_1902_08115_amd.autotune --out-dir gpurun_out
 
@@ -61,7 +63,7 @@ def header(table, skinny):
         return chr(10).join(rows)
     dims = ", ".join(str(x) if x < (1 << 30) else "1 << 30" for x in CLASS_MAX)
     sk = chr(10).join("    {" + chr(10) + block(skinny[c], "        ") + chr(10) + "    },"
-                      for c in range(3))
+                      for c in range(len(skinny)))
     return f"""// gemm_tuned.h -- size-class dispatch tables of the batched dgemm.
 //
 // Written by paper_1902_08115_amd/autotune.py from measurements on MI355X
@@ -69,9 +71,12 @@ def header(table, skinny):
 // by re-running the tuner.
 // Square table (m > 16 and n > 16): entry e for trans case (2*ta + tb)
 // applies while max(m, n, k) <= kGemmTuneMaxDim[e].  Skinny tables
-// kGemmSkinny[s]: s = 0 for m <= 16 and n <= 16 (class of k; the square
-// sizes up to 16 fall here), s = 1 for m <= 16 < n (class of max(n, k)),
-// s = 2 for n <= 16 < m (class of max(m, k)).  Variant 1 = direct kernel,
+// kGemmSkinny[s]: s = 0 for m <= 16 and n <= 16 but not both <= 4 (class of
+// k; the square sizes 8..16 and m = n = 16 with k above 16), s = 1 for
+// m <= 16 < n (class of max(n, k)), s = 2 for n <= 16 < m (class of
+// max(m, k)), s = 3 for m <= 4 and n <= 4 (class of k; m = n = 4).  A
+// choice within 2% of the fastest candidate is kept from the previous
+// table, so that run-to-run noise does not move it.  Variant 1 = direct kernel,
 // 2 = packed kernel with the given configuration of the packed menu,
 // 3 = register tiles (one 16-wide MFMA block per side of 16 or less, two
 // otherwise).
@@ -87,12 +92,40 @@ constexpr int kGemmTune[4][kGemmTuneEntries][2] = {{
 }};
 
 // {{variant, packed configuration}} per skinny class, trans case and size class
-constexpr int kGemmSkinny[3][4][kGemmTuneEntries][2] = {{
+constexpr int kGemmSkinny[{len(skinny)}][4][kGemmTuneEntries][2] = {{
 {sk}
 }};
 
 }}  // namespace mb
 """
+
+
+def committed_tables(path):
+    """The square and skinny tables of an existing gemm_tuned.h, as lists of
+    {trans: [(variant, config) per class]} (None if it cannot be read)."""
+    import re
+    try:
+        text = open(path).read()
+    except OSError:
+        return None, []
+    def pairs(body):
+        return [(int(a), int(b)) for a, b in re.findall(r"\{(-?\d+), (-?\d+)\}", body)]
+    ne = len(CLASS_MAX)
+    sq = re.search(r"kGemmTune\[4\]\[kGemmTuneEntries\]\[2\] = \{(.*?)\n\};", text, re.S)
+    sk = re.search(r"kGemmSkinny\[(\d+)\]\[4\]\[kGemmTuneEntries\]\[2\] = \{(.*?)\n\};", text, re.S)
+    if not sq or not sk or f"kGemmTuneEntries = {ne};" not in text:
+        return None, []
+    def split(p):
+        return {t: p[i * ne:(i + 1) * ne] for i, t in enumerate(TRANS)}
+    sqp, skp = pairs(sq.group(1)), pairs(sk.group(2))
+    nsk = int(sk.group(1))
+    if len(sqp) != 4 * ne or len(skp) != nsk * 4 * ne:
+        return None, []
+    return split(sqp), [split(skp[c * 4 * ne:(c + 1) * 4 * ne]) for c in range(nsk)]
+
+
+def class_index(x):
+    return next(i for i, cm in enumerate(CLASS_MAX) if x <= cm)
 
 
 def fused_header(c):
@@ -283,6 +316,8 @@ def main():
     ap.add_argument("--sizes", default=None)
     ap.add_argument("--fused", action="store_true", help="tune the fused uneven batch")
     ap.add_argument("--square-only", action="store_true", help="skip the thin / flat sweeps")
+    ap.add_argument("--keep-within", type=float, default=0.02,
+                    help="keep the committed choice when it is this close to the fastest")
     args = ap.parse_args()
     if args.fused:
         fused_tune(args)
@@ -297,9 +332,24 @@ def main():
     names = [_lib.dgemm_config_name(c) for c in range(ncfg)]
     limit = [_lib.dgemm_config_max_mn(c) for c in range(ncfg)]
     results = []
+    old_sq, old_sk = committed_tables(os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                   "csrc", "gemm_tuned.h"))
 
-    def measure(m, n, k, t, label):
-        """Time every applicable candidate on a ~1 GiB batch of (m, n, k)."""
+    def incumbent(table, t, x):
+        """The committed choice of class x in table (None: no such table)."""
+        if table is None:
+            return None
+        v, c = table[t][class_index(x)]
+        if v == 1:
+            return "direct"
+        if v == 3:
+            return "regtile"
+        return names[c] if 0 <= c < ncfg else None
+
+    def measure(m, n, k, t, label, inc=None):
+        """Time every applicable candidate on a ~1 GiB batch of (m, n, k); the
+        committed choice inc is kept when it is within --keep-within of the
+        fastest."""
         ar, ac = (m, k) if t[0] == "N" else (k, m)
         br, bc = (k, n) if t[1] == "N" else (n, k)
         batch = min(1 << 22, (1 << 30) // (8 * (m * k + k * n + m * n)))
@@ -324,10 +374,14 @@ def main():
                                                            cfg, sh)
                     assert st == 0, st
             timings[name] = time_call(torch, fn, args.reps)
-        win = min(timings, key=timings.get)
+        fastest = min(timings, key=timings.get)
+        win = fastest
+        if inc in timings and timings[inc] <= (1.0 + args.keep_within) * timings[fastest]:
+            win = inc
         flops = 2.0 * m * n * k * batch
         results.append({"sweep": label, "m": m, "n": n, "k": k, "trans": t, "batch": batch,
-                        "ms": timings, "best": win, "best_gflops": flops / timings[win] / 1e6})
+                        "ms": timings, "best": win, "fastest": fastest, "incumbent": inc,
+                        "best_gflops": flops / timings[win] / 1e6})
         log(f"{label} {m}x{n}x{k} {t}: best {win} {flops / timings[win] / 1e6:.0f} GF/s " + " ".join(
             f"{kk.replace('gemm_packed_', '')}={v:.3f}" for kk, v in timings.items()))
         del A, B, C
@@ -353,27 +407,42 @@ def main():
             table[t] = row
         return table
 
+    # the committed skinny tables: 4 classes, or the earlier 3 (no tiny class;
+    # class 0 then held m = n = 4 for k above 16 and the square sizes below)
+    old4 = len(old_sk) == 4
+    inc_tiny = old_sk[3] if old4 else None
     square = {t: {} for t in TRANS}
-    skinny = [{t: {} for t in TRANS} for _ in range(3)]
+    skinny = [{t: {} for t in TRANS} for _ in range(4)]
     for n in sizes:
         for t in TRANS:
-            choice = measure(n, n, n, t, "square")
             if n > 16:
-                square[t][n] = choice
-            else:
-                skinny[0][t][n] = choice   # m, n <= 16: the small table
+                square[t][n] = measure(n, n, n, t, "square", incumbent(old_sq, t, n))
+            elif n <= 4:   # m, n <= 4: the tiny table
+                inc = incumbent(inc_tiny if old4 else (old_sk[0] if old_sk else None), t, n)
+                skinny[3][t][n] = measure(n, n, n, t, "square", inc)
+            else:          # m, n <= 16: the small table
+                inc = incumbent(old_sk[0] if old_sk else None, t, n)
+                skinny[0][t][n] = measure(n, n, n, t, "square", inc)
     if not args.square_only:
-        for s in [x for x in sizes if x > 16]:
+        for s in [x for x in sizes if x > 4]:
             for t in TRANS:
-                skinny[0][t][s] = measure(4, 4, s, t, "m=n=4")
-                skinny[1][t][s] = measure(4, s, s, t, "m=4")
-                skinny[2][t][s] = measure(s, 4, s, t, "n=4")
+                if s <= 16:  # m = n = 4 with short k (square sizes above 4 are 8..16)
+                    skinny[3][t][s] = measure(4, 4, s, t, "m=n=4", incumbent(inc_tiny, t, s))
+                    continue
+                inc = incumbent(inc_tiny if old4 else (old_sk[0] if old_sk else None), t, s)
+                skinny[3][t][s] = measure(4, 4, s, t, "m=n=4", inc)
+                skinny[0][t][s] = measure(16, 16, s, t, "m=n=16",
+                                          incumbent(old_sk[0] if old4 else None, t, s))
+                skinny[1][t][s] = measure(4, s, s, t, "m=4",
+                                          incumbent(old_sk[1] if old_sk else None, t, s))
+                skinny[2][t][s] = measure(s, 4, s, t, "n=4",
+                                          incumbent(old_sk[2] if old_sk else None, t, s))
     for t in TRANS:  # classes below every measured size take the smallest measured one
         for d in [square] + skinny:
             if not d[t]:
                 d[t] = {16: (3, -1)}
     table = to_table(square)
-    sk = [to_table(skinny[c]) for c in range(3)]
+    sk = [to_table(skinny[c]) for c in range(4)]
     os.makedirs(args.out_dir, exist_ok=True)
     with open(os.path.join(args.out_dir, "gemm_tuned.h"), "w") as f:
         f.write(header(table, sk))

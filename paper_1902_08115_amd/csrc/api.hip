@@ -50,12 +50,16 @@ int size_class(int m, int n, int k)
 // square table (class of max(m, n, k)); thin (n <= 16), flat (m <= 16) and
 // small results use the skinny tables, so that the choice follows the
 // shape of C as the paper's variant switch does for rectangular matrices
-// (Sec. 2.3.2, App. C).
+// (Sec. 2.3.2, App. C).  Results of at most 4 x 4 have a table of their own:
+// there one 16-wide MFMA tile is mostly padding and the direct kernel can
+// win at any k, which the m, n <= 16 table (tuned on 8..16) would hide.
 const int *table_entry(int ta, int tb, int m, int n, int k)
 {
     const int tc = 2 * ta + tb;
     if (m > 16 && n > 16)
         return mb::kGemmTune[tc][size_class(m, n, k)];
+    if (m <= 4 && n <= 4)
+        return mb::kGemmSkinny[3][tc][dim_class(k)];
     if (m <= 16 && n <= 16)
         return mb::kGemmSkinny[0][tc][dim_class(k)];
     if (m <= 16)

@@ -369,3 +369,21 @@ def test_ceiling_probe_argument_errors(L):
     assert L.lib.mb_ceiling_fp64(1, 1, 0, buf, ctypes.byref(fl), None) == -3
     assert L.lib.mb_ceiling_fp64(0, 1, 1, None, ctypes.byref(fl), None) == -4
     assert L.lib.mb_ceiling_fp64(0, 1, 1, buf, None, None) == -5
+
+
+def test_tuned_tables_parse_and_tiny_dispatch(L):
+    """The committed dispatch tables parse back (the autotuner keeps their
+    choices within its noise margin) and re-emit byte for byte; results of at
+    most 4 x 4 take the tiny table's choice, 16 x 16 the m, n <= 16 table's."""
+    from paper_1902_08115_amd import autotune
+    path = os.path.join(ROOT, "paper_1902_08115_amd", "csrc", "gemm_tuned.h")
+    sq, sk = autotune.committed_tables(path)
+    assert sq is not None and len(sk) == 4
+    assert autotune.header(sq, sk) == open(path).read()
+    for t in autotune.TRANS:
+        for k in (1, 4, 8, 12, 16, 24, 300):
+            e = autotune.class_index(k)
+            assert L.dgemm_select(t[0], t[1], 4, 4, k) == sk[3][t][e][0], (t, k)
+            assert L.dgemm_select(t[0], t[1], 3, 2, k) == sk[3][t][e][0], (t, k)
+            assert L.dgemm_select(t[0], t[1], 16, 16, k) == sk[0][t][e][0], (t, k)
+            assert L.dgemm_select(t[0], t[1], 16, 5, k) == sk[0][t][e][0], (t, k)

@@ -298,7 +298,7 @@ def test_packed_huge_leading_dimension(trans):
 
 SKINNY = [(4, 4, 1), (4, 4, 2), (4, 4, 3), (4, 4, 17), (4, 4, 300), (1, 300, 5), (4, 300, 300),
           (4, 37, 200), (16, 17, 33), (300, 4, 300), (97, 4, 15), (17, 16, 9), (3, 5, 300),
-          (16, 16, 257), (33, 2, 64)]
+          (16, 16, 257), (33, 2, 64), (2, 3, 8), (4, 4, 12)]
 
 
 @pytest.mark.parametrize("variant", ["auto", "regtile"])
