@@ -13,12 +13,44 @@
 // whose loads are all issued before the first product of the chunk, and C is
 // read up front, so k <= KC costs one round trip instead of one per k step.
 // KC = 4 measured best at every square size up to 16 (chunks of 8 hold more
-// loads in flight but cost a wave per SIMD).
+// loads in flight but cost a wave per SIMD).  Whole chunks and the ragged
+// last one are separate code: in a whole chunk a thread's k steps of one
+// operand row or column, and (n a multiple of RN) its RN columns of a
+// transposed B, are consecutive addresses that the compiler fetches with
+// 16-byte loads -- fewer load instructions, which bound the rate at n = 8.
 #include "mb_internal.h"
 
 namespace mb {
 
-template <bool TA, bool TB, int RN, int KC>
+// One chunk of KC k steps: all loads first, then the products in k order.
+// FULL: every k step of the chunk exists; otherwise steps past the end load
+// the last valid one and skip its product.
+template <bool TA, bool TB, int RN, int KC, bool FULL>
+__device__ __forceinline__ void direct_chunk(const double *A, const double *B, size_t lda,
+                                             size_t ldb, int i, const int (&jc)[RN], int q0,
+                                             int k, double (&acc)[RN])
+{
+    double av[KC], bv[KC][RN];
+#pragma unroll
+    for (int u = 0; u < KC; ++u) {
+        const size_t q = (size_t)(FULL ? q0 + u : min(q0 + u, k - 1));
+        av[u] = TA ? A[q + (size_t)i * lda] : A[(size_t)i + q * lda];
+#pragma unroll
+        for (int r = 0; r < RN; ++r)
+            bv[u][r] = TB ? B[(size_t)jc[r] + q * ldb] : B[q + (size_t)jc[r] * ldb];
+    }
+#pragma unroll
+    for (int u = 0; u < KC; ++u) {
+        if (FULL || q0 + u < k) {
+#pragma unroll
+            for (int r = 0; r < RN; ++r)
+                acc[r] = fma(av[u], bv[u][r], acc[r]);
+        }
+    }
+}
+
+// NC: n is a multiple of RN, so a thread's columns j0 .. j0 + RN - 1 all exist.
+template <bool TA, bool TB, int RN, int KC, bool NC>
 __global__ __launch_bounds__(256) void gemm_direct_kernel(GemmArgs p, int per_inst, int ipb)
 {
     const int t = threadIdx.x;
@@ -51,7 +83,7 @@ __global__ __launch_bounds__(256) void gemm_direct_kernel(GemmArgs p, int per_in
     int jc[RN];
 #pragma unroll
     for (int r = 0; r < RN; ++r)
-        jc[r] = min(j0 + r, p.n - 1);
+        jc[r] = NC ? j0 + r : min(j0 + r, p.n - 1);
 
     // beta == 0: C is not read
     const bool read_c = p.beta != 0.0;
@@ -65,31 +97,17 @@ __global__ __launch_bounds__(256) void gemm_direct_kernel(GemmArgs p, int per_in
     for (int r = 0; r < RN; ++r)
         acc[r] = 0.0;
 
-    for (int q0 = 0; q0 < k; q0 += KC) {
-        // a chunk's k indices past the end load the last valid one; their
-        // products are skipped, so the sum runs over q = 0..k-1 in order
-        double av[KC], bv[KC][RN];
-#pragma unroll
-        for (int u = 0; u < KC; ++u) {
-            const size_t q = (size_t)min(q0 + u, k - 1);
-            av[u] = TA ? A[q + (size_t)i * lda] : A[(size_t)i + q * lda];
-#pragma unroll
-            for (int r = 0; r < RN; ++r)
-                bv[u][r] = TB ? B[(size_t)jc[r] + q * ldb] : B[q + (size_t)jc[r] * ldb];
-        }
-#pragma unroll
-        for (int u = 0; u < KC; ++u) {
-            if (q0 + u < k) {
-#pragma unroll
-                for (int r = 0; r < RN; ++r)
-                    acc[r] = fma(av[u], bv[u][r], acc[r]);
-            }
-        }
-    }
+    // whole chunks, then the ragged last one: the sum runs over q = 0..k-1
+    // in order either way
+    int q0 = 0;
+    for (; q0 + KC <= k; q0 += KC)
+        direct_chunk<TA, TB, RN, KC, true>(A, B, lda, ldb, i, jc, q0, k, acc);
+    if (q0 < k)
+        direct_chunk<TA, TB, RN, KC, false>(A, B, lda, ldb, i, jc, q0, k, acc);
 #pragma unroll
     for (int r = 0; r < RN; ++r) {
         const int j = j0 + r;
-        if (j < p.n)
+        if (NC || j < p.n)
             C[(size_t)i + (size_t)j * ldc] = read_c ? fma(p.alpha, acc[r], p.beta * cv[r])
                                                     : p.alpha * acc[r];
     }
@@ -108,8 +126,8 @@ __global__ __launch_bounds__(256) void gemm_scale_kernel(GemmArgs p)
     }
 }
 
-template <bool TA, bool TB>
-static hipError_t launch_direct_t(const GemmArgs &a, hipStream_t s)
+template <bool TA, bool TB, bool NC>
+static hipError_t launch_direct_n(const GemmArgs &a, hipStream_t s)
 {
     constexpr int RN = 4, KC = 4;
     const int nb = (a.n + RN - 1) / RN;
@@ -120,14 +138,20 @@ static hipError_t launch_direct_t(const GemmArgs &a, hipStream_t s)
     if (per_inst <= 256) {
         const int ipb = 256 / per_inst;
         const int64_t blocks = ((int64_t)a.batch + ipb - 1) / ipb;
-        hipLaunchKernelGGL((gemm_direct_kernel<TA, TB, RN, KC>), dim3((unsigned)blocks), dim3(256), 0,
+        hipLaunchKernelGGL((gemm_direct_kernel<TA, TB, RN, KC, NC>), dim3((unsigned)blocks), dim3(256), 0,
                            s, a, per_inst, ipb);
     } else {
         const int gy = (per_inst + 255) / 256;
-        hipLaunchKernelGGL((gemm_direct_kernel<TA, TB, RN, KC>), dim3((unsigned)a.batch, gy),
+        hipLaunchKernelGGL((gemm_direct_kernel<TA, TB, RN, KC, NC>), dim3((unsigned)a.batch, gy),
                            dim3(256), 0, s, a, per_inst, 0);
     }
     return hipGetLastError();
+}
+
+template <bool TA, bool TB>
+static hipError_t launch_direct_t(const GemmArgs &a, hipStream_t s)
+{
+    return a.n % 4 == 0 ? launch_direct_n<TA, TB, true>(a, s) : launch_direct_n<TA, TB, false>(a, s);
 }
 
 hipError_t launch_gemm_direct(bool ta, bool tb, const GemmArgs &a, hipStream_t s)
