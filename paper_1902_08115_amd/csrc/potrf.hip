@@ -10,7 +10,13 @@ namespace mb {
 template <int NT, int IPB>
 __global__ __launch_bounds__(IPB * 64) __attribute__((amdgpu_waves_per_eu(2))) void potrf_lower_kernel(PotrfArgs p)
 {
+    // orders from 12 tiles keep their first KC pivot steps per pair in LDS
+    // (2 KC tiles of 2 KB per wave: 64 KB for four waves, two workgroups per
+    // CU -- the two waves per SIMD their registers allow); n = 256..304 run
+    // 6-9% faster, n = 192..240 1.5-3%, and n = 128..160 gained nothing
+    constexpr int KC = NT >= 12 ? 4 : 0;
     __shared__ PotrfSmem smem[IPB];
+    __shared__ double pcache[IPB][KC > 0 ? 2 * KC * 256 : 1];
     const int lane = threadIdx.x & 63;
     const int inst = threadIdx.x >> 6;
     const int64_t b = (int64_t)blockIdx.x * IPB + inst;
@@ -32,7 +38,8 @@ __global__ __launch_bounds__(IPB * 64) __attribute__((amdgpu_waves_per_eu(2))) v
     // n = 256), two where three would spill (NT = 17, 19); the plain-loop
     // orders keep none -- there the extra registers cost a wave per SIMD
     constexpr int G1 = PIPE ? ((NT == 17 || NT == 19) ? 2 : 3) : 0;
-    const int info = potrf_wave<true, G, PIPE, UNROLL, G1>(A, (size_t)p.lda, p.n, NT, smem[inst], lane);
+    const int info = potrf_wave<true, G, PIPE, UNROLL, G1, KC>(A, (size_t)p.lda, p.n, NT, smem[inst],
+                                                                lane, pcache[inst]);
     if (lane == 0)
         p.info[b] = info;
 }

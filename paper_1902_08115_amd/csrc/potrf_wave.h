@@ -17,7 +17,9 @@
 // are processed two at a time, so every factored tile loaded for the update
 // serves both (half the re-reads of the factor, more registers); with G1 the
 // first G1 panel rows are updated in the diagonal block's loop, which loads
-// the pivot tiles L(J,K), L(J1,K) they need anyway.  For one block column J:
+// the pivot tiles L(J,K), L(J1,K) they need anyway; with KC the diagonal
+// block's loop also leaves the pivot tiles of its first KC steps in LDS, from
+// where the later panel groups take them.  For one block column J:
 //   1. tile(J,J) of A minus L(J,K) * L(J,K)^T for every factored block column
 //      K < J: four MFMA steps per K whose operands are the registers s of
 //      L(J,K) loaded from the factor already written (the k index of step s in
@@ -222,12 +224,33 @@ __device__ __forceinline__ d4 update_nt(d4 acc, const d4 &x, const d4 &y)
     return acc;
 }
 
+// A tile kept in LDS in accumulator order: slot t, register r, lane.  Each
+// lane reads back only the values it wrote itself.
+__device__ __forceinline__ void lds_put_tile(double *pc, int t, const d4 &x, int lane)
+{
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        pc[(t * 4 + r) * 64 + lane] = x[r];
+}
+
+__device__ __forceinline__ d4 lds_get_tile(const double *pc, int t, int lane)
+{
+    d4 x;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        x[r] = pc[(t * 4 + r) * 64 + lane];
+    return x;
+}
+
 // Factor the n x n lower triangle of A (nt = ceil(n / 16) tiles) with the
 // calling wave; returns the LAPACK info (0, or the failing column + 1).  S is
-// this wave's private LDS block.
-template <bool PAIR, int G = 2, bool PIPE = true, bool UNROLL = false, int G1 = 0>
+// this wave's private LDS block.  With KC > 0, pc is this wave's LDS slot of
+// 2 KC tiles: the diagonal block's loop keeps the
+// pivot tiles L(J,K), L(J1,K) of its first KC steps there, and every later
+// panel group takes those steps from LDS instead of reading them again.
+template <bool PAIR, int G = 2, bool PIPE = true, bool UNROLL = false, int G1 = 0, int KC = 0>
 __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT, PotrfSmem &S,
-                                          int lane)
+                                          int lane, double *pc = nullptr)
 {
     MB_GLOBAL double *A = global_ptr(Ain);
     // G: panel row tiles updated together (register footprint grows with G)
@@ -280,6 +303,10 @@ __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT
                     t10 = update_nt(t10, l1, l0);
                     t11 = update_nt(t11, l1, l1);
                 }
+                if (KC > 0 && K < KC) {
+                    lds_put_tile(pc, 2 * K, l0, lane);
+                    lds_put_tile(pc, 2 * K + 1, l1, lane);
+                }
                 if constexpr (G1 > 0) {
 #pragma unroll
                     for (int g = 0; g < NF; ++g) {
@@ -302,6 +329,10 @@ __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT
                 pf[g] = G1 > 0 ? load_tile(A, lda, n, F0 + g, 0, lr, lg, false) : d4{0.0, 0.0, 0.0, 0.0};
             for (int K = 0; K < J; ++K) {
                 const d4 l0 = p0, l1 = p1;
+                if (KC > 0 && K < KC) {
+                    lds_put_tile(pc, 2 * K, l0, lane);
+                    lds_put_tile(pc, 2 * K + 1, l1, lane);
+                }
                 d4 lf[NF];
 #pragma unroll
                 for (int g = 0; g < NF; ++g)
@@ -372,7 +403,22 @@ __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT
                                     : d4{0.0, 0.0, 0.0, 0.0};
             }
             if (!PIPE) {
-                for (int K = 0; K < J; ++K) {
+                // steps below Kc take the pivot tiles from the LDS cache
+                const int Kc = KC > 0 ? min(J, KC) : 0;
+                for (int K = 0; K < Kc; ++K) {
+                    const d4 l0 = lds_get_tile(pc, 2 * K, lane);
+                    const d4 l1 = lds_get_tile(pc, 2 * K + 1, lane);
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        if (I0 + g < NT) {
+                            const d4 li = load_tile(A, lda, n, I0 + g, K, lr, lg, false);
+                            a0[g] = update_nt(a0[g], li, l0);
+                            if (two)
+                                a1[g] = update_nt(a1[g], li, l1);
+                        }
+                    }
+                }
+                for (int K = Kc; K < J; ++K) {
                     const d4 l0 = load_tile(A, lda, n, J, K, lr, lg, false);
                     const d4 l1 = two ? load_tile(A, lda, n, J1, K, lr, lg, false)
                                       : d4{0.0, 0.0, 0.0, 0.0};
@@ -387,13 +433,38 @@ __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT
                     }
                 }
             } else if (J > 0) {
-                d4 p0 = load_tile(A, lda, n, J, 0, lr, lg, false);
-                d4 p1 = load_tile(A, lda, n, R1, 0, lr, lg, false);
+                // steps below Kc take the pivot tiles from the LDS cache
+                const int Kc = KC > 0 ? min(J, KC) : 0;
                 d4 pi[G];
 #pragma unroll
                 for (int g = 0; g < G; ++g)
                     pi[g] = load_tile(A, lda, n, I0 + g, 0, lr, lg, false);
-                for (int K = 0; K < J; ++K) {
+                for (int K = 0; K < Kc; ++K) {
+                    const d4 l0 = lds_get_tile(pc, 2 * K, lane);
+                    const d4 l1 = lds_get_tile(pc, 2 * K + 1, lane);
+                    d4 li[G];
+#pragma unroll
+                    for (int g = 0; g < G; ++g)
+                        li[g] = pi[g];
+                    const int Kn = min(K + 1, J - 1);
+#pragma unroll
+                    for (int g = 0; g < G; ++g)
+                        pi[g] = load_tile(A, lda, n, I0 + g, Kn, lr, lg, false);
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        if (I0 + g < NT) {
+                            a0[g] = update_nt(a0[g], li[g], l0);
+                            if (two)
+                                a1[g] = update_nt(a1[g], li[g], l1);
+                        }
+                    }
+                }
+                d4 p0 = d4{0.0, 0.0, 0.0, 0.0}, p1 = d4{0.0, 0.0, 0.0, 0.0};
+                if (Kc < J) {
+                    p0 = load_tile(A, lda, n, J, Kc, lr, lg, false);
+                    p1 = load_tile(A, lda, n, R1, Kc, lr, lg, false);
+                }
+                for (int K = Kc; K < J; ++K) {
                     const d4 l0 = p0, l1 = p1;
                     d4 li[G];
 #pragma unroll

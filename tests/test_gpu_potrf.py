@@ -54,7 +54,8 @@ def test_sweep_sizes_with_failing_instance(si, n):
         assert d <= POTRF_TOL, d
 
 
-@pytest.mark.parametrize("n", [1, 2, 5, 15, 16, 17, 31, 33, 47, 64, 65, 100, 129, 200, 256, 300])
+@pytest.mark.parametrize("n", [1, 2, 5, 15, 16, 17, 31, 33, 47, 64, 65, 100, 129, 200, 256, 272,
+                               288, 300])
 def test_exact_integer_factor(n):
     """A = L0 L0^T with integer L0 (diagonal in {1,2,4}): the factor is L0
     exactly for any evaluation order, so the GPU result must match bit for bit."""
