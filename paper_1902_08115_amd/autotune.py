@@ -15,7 +15,7 @@ kernel menu of this library.  A class keeps the choice of the committed
 gemm_tuned.h while that choice is within --keep-within (2%) of the fastest
 candidate, so repeated runs do not reshuffle near-ties.  Needs a GPU:
 
-  python -m paper_1902_08115_amd.autotune --out-dir gpurun_out
+  python -m paper_1902_08115_amd.autotune --out-dir out
 
 With --fused it tunes the fused uneven batch instead and writes
 fused_tuned.h: the wave time of every task kind is measured on homogeneous

@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     """Skip GPU tests cleanly when no GPU is present (they still fail loudly on
-    a GPU box whose HIP library is missing: see tests/gpu_util.py)."""
+    a GPU machine whose HIP library is missing: see tests/gpu_util.py)."""
     try:
         import torch
         has_gpu = torch.cuda.is_available()
