@@ -10,11 +10,10 @@ namespace mb {
 template <int NT, int IPB>
 __global__ __launch_bounds__(IPB * 64) __attribute__((amdgpu_waves_per_eu(2))) void potrf_lower_kernel(PotrfArgs p)
 {
-    // orders from 12 tiles keep their first KC pivot steps per pair in LDS
+    // orders from 8 tiles keep their first KC pivot steps per pair in LDS
     // (2 KC tiles of 2 KB per wave: 64 KB for four waves, two workgroups per
-    // CU -- the two waves per SIMD their registers allow); n = 256..304 run
-    // 6-9% faster, n = 192..240 1.5-3%, and n = 128..160 gained nothing
-    constexpr int KC = NT >= 12 ? 4 : 0;
+    // CU -- the two waves per SIMD their registers allow)
+    constexpr int KC = NT >= 8 ? 4 : 0;
     __shared__ PotrfSmem smem[IPB];
     __shared__ double pcache[IPB][KC > 0 ? 2 * KC * 256 : 1];
     const int lane = threadIdx.x & 63;
@@ -23,21 +22,22 @@ __global__ __launch_bounds__(IPB * 64) __attribute__((amdgpu_waves_per_eu(2))) v
     if (b >= p.batch)
         return;  // each wave is its own instance: nothing to synchronise with
     double *A = inst_ptr(p.A, p.Aarr, p.sA, b);
-    // the pipelined update loops need more registers; they measured faster at
-    // n = 256 and slower at n = 64, 128 and 192 (same occupancy or one wave
-    // per SIMD less), so only the largest orders use them
-    constexpr bool PIPE = NT >= 16;
+    // the pipelined update loops (with the LDS pivot cache) measured 3-12%
+    // faster than the plain ones from 8 tiles (n = 128..240) and faster at
+    // n = 256..304; below 8 tiles the plain loops keep more waves per SIMD
+    constexpr bool PIPE = NT >= 8;
     // one tile: the unrolled diagonal factorization costs no occupancy there
     constexpr bool UNROLL = NT == 1;
     // panel rows per group: more rows share each load of the pivot columns'
-    // tiles (fewer re-reads) at more registers -- 4 up to NT = 12, 3 with the
-    // pipelined loops (4 would spill there), measured 1-2% faster than 2
-    constexpr int G = NT >= 13 ? 3 : (NT >= 8 ? 4 : 2);
+    // tiles (fewer re-reads) at more registers -- 3 with the pipelined loops
+    // (4 would spill there), 2 below 8 tiles
+    constexpr int G = PIPE ? 3 : 2;
     // first panel rows updated inside the diagonal-block loop (they share its
     // pivot tiles): three rows with the pipelined loops (4.8% faster at
-    // n = 256), two where three would spill (NT = 17, 19); the plain-loop
-    // orders keep none -- there the extra registers cost a wave per SIMD
-    constexpr int G1 = PIPE ? ((NT == 17 || NT == 19) ? 2 : 3) : 0;
+    // n = 256), two where three would spill (odd tile counts, and below 12
+    // tiles); the plain-loop orders keep none -- there the extra registers
+    // cost a wave per SIMD
+    constexpr int G1 = PIPE ? ((NT % 2 == 1 || NT < 12) ? 2 : 3) : 0;
     const int info = potrf_wave<true, G, PIPE, UNROLL, G1, KC>(A, (size_t)p.lda, p.n, NT, smem[inst],
                                                                 lane, pcache[inst]);
     if (lane == 0)
