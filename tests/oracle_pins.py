@@ -465,6 +465,43 @@ def pin_adjoint_finite_differences(lib, seed=32, h=1e-6):
             assert abs(fd - an) <= 1e-6 * (abs(fd) + 1e-300) + 1e-9, f"n={n}: fd {fd} vs {an}"
 
 
+def pin_adjoint_batched_matches_single(lib, seed=33):
+    """The strided-batched adjoint equals a loop of single adjoints bit for bit
+    when L, Lbar and Abar each have their own leading dimension and instance
+    stride, with NaN in every gap between instances and in every ld padding:
+    a stride or ld taken from the wrong operand, or an instance skipped, reads
+    a NaN (or writes the wrong place) and fails."""
+    g = _rng(seed)
+    n, batch = 7, 5
+    lds = {"L": n + 2, "Lb": n + 5, "Ab": n + 1}
+    strides = {"L": lds["L"] * n + 3, "Lb": lds["Lb"] * n + 11, "Ab": lds["Ab"] * n + 6}
+    bufs = {k: np.full(strides[k] * batch, np.nan) for k in lds}
+    Ls, Lbs = [], []
+    for b in range(batch):
+        L = _chol(_spd(g, n), lib)
+        W = np.tril(g.uniform(-1, 1, size=(n, n)))
+        Ls.append(L)
+        Lbs.append(W)
+        for key, M in (("L", L), ("Lb", W)):
+            blk = np.full((lds[key], n), np.nan, order="F")
+            blk[:n] = M
+            blk[:n][np.triu_indices(n, 1)] = np.nan  # strict upper parts are never read
+            bufs[key][b * strides[key]:b * strides[key] + lds[key] * n] = blk.ravel(order="F")
+    Ab = bufs["Ab"].copy()
+    oracle.dpotrf_l_adjoint_strided_batched(n, bufs["L"], lds["L"], strides["L"], bufs["Lb"],
+                                            lds["Lb"], strides["Lb"], Ab, lds["Ab"],
+                                            strides["Ab"], batch, nthreads=3, lib=lib)
+    expect = bufs["Ab"].copy()
+    for b in range(batch):
+        ref = oracle.dpotrf_l_adjoint(Ls[b], Lbs[b], lib=lib)
+        blk = expect[b * strides["Ab"]:b * strides["Ab"] + lds["Ab"] * n].reshape(
+            (lds["Ab"], n), order="F").copy(order="F")
+        blk[:n] = ref
+        expect[b * strides["Ab"]:b * strides["Ab"] + lds["Ab"] * n] = blk.ravel(order="F")
+    assert np.isfinite(ref).all()
+    assert np.array_equal(Ab, expect, equal_nan=True)
+
+
 # ---------------------------------------------------------------- dtrmm / dsyrk
 
 
@@ -731,6 +768,7 @@ ALL_PINS = [
     pin_adjoint_logdet,
     pin_adjoint_n1,
     pin_adjoint_finite_differences,
+    pin_adjoint_batched_matches_single,
     pin_trmm_exact_bruteforce,
     pin_syrk_exact_bruteforce,
     pin_trmm_syrk_scipy,

@@ -44,6 +44,12 @@ MUTANTS = [
      "for (int p = i + 1; p < n; ++p)\n                    v +="),
     ("adjoint_transposed_L", "v -= Lx(p, i) * Px(p, j);", "v -= Lx(i, p) * Px(p, j);"),
     ("adjoint_second_solve_sign", "v -= Px(r, p) * Lx(p, c);", "v += Px(r, p) * Lx(p, c);"),
+    ("adjoint_batched_swapped_strides", "Lbar + (ptrdiff_t)b * strideLb, ldlb,",
+     "Lbar + (ptrdiff_t)b * strideL, ldlb,"),
+    ("adjoint_batched_swapped_ld", "Lbar + (ptrdiff_t)b * strideLb, ldlb,",
+     "Lbar + (ptrdiff_t)b * strideLb, ldl,"),
+    ("adjoint_batched_skips_first", "        bad |= oracle_dpotrf_l_adjoint(n, L + (ptrdiff_t)b",
+     "        if (b > 0) bad |= oracle_dpotrf_l_adjoint(n, L + (ptrdiff_t)b"),
     ("trmm_reads_upper", "* A[(size_t)p + (size_t)j * (size_t)lda];\n            B[",
      "* A[(size_t)j + (size_t)p * (size_t)lda];\n            B["),
     ("trmm_dropped_diagonal", "for (int p = j; p < n; ++p)\n                s += B",
