@@ -10,7 +10,11 @@ One step is one pass of the whole hot path over resident synthetic inputs:
 Every call goes through the C ABI of libmi355blas.so on torch's current
 stream; per-launch durations come from events recorded on that stream.
 
-Prints ONE JSON line on stdout; progress goes to stderr.
+Prints ONE compact JSON line on stdout (the headline, the dominant kernel's
+roofline, the CPU baseline, GFLOP/s against n); progress goes to stderr, and
+so does the full record (per size, per kernel class, the uneven-batch,
+differentiation and Riccati workloads) as one `[bench] details {...}` line,
+also written to --details-out when given.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
   python bench.py --crossover     # direct vs packed dgemm at every sweep size
@@ -144,7 +148,7 @@ def run_step(step, gemm, potrf, _lib, stream, timer, restore_counter):
                 timer.around(("dgemm", trans, n), call)
     for (n, batch, master, copies, info, _) in potrf:
         c = step % len(copies)
-        if step >= len(copies):  # this copy was factored before: restore it (timed)
+        if step >= len(copies):  # this copy was factored before: restore it (inside the step)
             copies[c].copy_(master)
             restore_counter[0] += 2 * master.numel() * 8
 
@@ -182,22 +186,43 @@ def ceilings(torch, _lib, stream):
             ms = e0.elapsed_time(e1)
             best = ms if best is None else min(best, ms)
         res[key] = round(fl / best / 1e9, 2)
-    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
-    src.fill_(1.0)
-    dst = torch.empty_like(src)
+    # HBM: the library's streaming probes (16-byte non-temporal accesses, four
+    # loads in flight per thread) over 1 GiB per stream -- far beyond the
+    # 256 MiB last-level cache -- at two grid sizes, best of 3 each; and
+    # torch's device-to-device copy beside them
+    n = 1 << 27
+    src = torch.ones(3 * n, dtype=torch.float64, device="cuda")
+    dst = torch.empty(n, dtype=torch.float64, device="cuda")
+    part = torch.empty(cus * 32 * 256, dtype=torch.float64, device="cuda")
+    for key, kind in (("hbm_read_gbps", 0), ("hbm_copy_gbps", 1), ("hbm_3r1w_gbps", 2)):
+        best = None
+        for blocks in (cus * 8, cus * 32):
+            for _ in range(3):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                st, by = _lib.ceiling_hbm(kind, src.data_ptr(), dst.data_ptr(), n, blocks,
+                                          part.data_ptr(), sh)
+                e1.record()
+                if st != 0:
+                    raise RuntimeError(f"mb_ceiling_hbm kind {kind}: status {st}")
+                torch.cuda.synchronize()
+                rate = by / e0.elapsed_time(e1) / 1e6
+                best = rate if best is None else max(best, rate)
+        res[key] = round(best, 1)
     best = None
     for _ in range(3):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        dst.copy_(src)
+        dst.copy_(src[:n])
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         best = ms if best is None else min(best, ms)
-    res["copy_gbps"] = round(2 * src.numel() * 8 / best / 1e6, 1)
+    res["torch_copy_gbps"] = round(2 * n * 8 / best / 1e6, 1)
     res["spec"] = {"fp64_tflops": PEAK_FP64_TFLOPS, "hbm_gbps": PEAK_HBM_GBS}
-    del src, dst, out
+    del src, dst, out, part
     torch.cuda.empty_cache()
     return res
 
@@ -579,6 +604,32 @@ def backward_workload(torch, _lib, inputs, reps):
                             "forward_gflops": round(ffl / f_best / 1e6, 1),
                             "backward_gflops": round(bfl / b_best / 1e6, 1)}
     log(f"backward n=64 x 8192: forward {f_best:.3f} ms, backward {b_best:.3f} ms")
+    # the Cholesky adjoint kernel alone (one launch over the 8192 instances):
+    # P = Phi(L^T Lbar) and the two triangular solves, about 5 n^3 / 3 flop;
+    # L and Lbar lower triangles read, Abar written whole
+    Lt = ag.cholesky(A.detach())
+    Lbar = torch.tril(inputs.torch_colmajor(batch, n, n, seed=inputs.seed_for(4, 5)))
+    Lbar = ag.colmajor(Lbar)
+    Abar = torch.empty_like(Lbar)
+    sh = torch.cuda.current_stream().cuda_stream
+
+    def adj():
+        st = _lib.dpotrf_l_backward_strided_batched(n, Lt.data_ptr(), n, n * n, Lbar.data_ptr(),
+                                                    n, n * n, Abar.data_ptr(), n, n * n, batch, sh)
+        assert st == 0, st
+    adj()
+    a_best, a_med = time_events(torch, adj, reps)
+    afl = batch * 5.0 * n ** 3 / 3
+    aby = batch * (8.0 * n * (n + 1) + 8.0 * n * n)
+    roof = min(PEAK_FP64_TFLOPS, afl / aby * PEAK_HBM_GBS / 1e3)
+    out["adjoint_kernel_n64_batch8192"] = {
+        "kernel": "potrf_adj_kernel", "ms": round(a_best, 4), "median_ms": round(a_med, 4),
+        "flops": afl, "algorithmic_bytes": aby, "gflops": round(afl / a_best / 1e6, 1),
+        "gbps": round(aby / a_best / 1e6, 1), "roofline_tflops": round(roof, 2),
+        "roof_frac": round(afl / a_best / 1e9 / roof, 3)}
+    log(f"cholesky adjoint kernel n=64 x 8192: {a_best:.3f} ms "
+        f"({out['adjoint_kernel_n64_batch8192']['roof_frac']} of its roofline)")
+    del Lt, Lbar, Abar
     ns = inputs.backward_mixed_sizes(inputs.seed_for(4, 10))
     mp = MixedCholeskyProduct(ns, nb)
     for v in np.unique(ns):
@@ -588,12 +639,27 @@ def backward_workload(torch, _lib, inputs, reps):
             mp.view("A", int(b)).copy_(S[j])
     gen = torch.Generator(device="cuda")
     mp.buf["B"].uniform_(-1.0, 1.0, generator=gen.manual_seed(12))
-    mp.buf["Cbar"].uniform_(-1.0, 1.0, generator=gen.manual_seed(13))
-    mp.forward()
-    mp.backward()
+    Wm = torch.empty_like(mp.buf["C"]).uniform_(-1.0, 1.0, generator=gen.manual_seed(13))
+    # through the autograd Function, on the object's own arenas (no input copies)
+    Am = mp.buf["A"].requires_grad_(True)
+    Bm = mp.buf["B"].requires_grad_(True)
+
+    def mfwd():
+        state["Cm"] = mp(Am, Bm)
+
+    def mbwd():
+        state["Cm"].backward(Wm)
+
+    def mfresh():
+        Am.grad = None
+        Bm.grad = None
+        mfwd()
+
+    mfwd()
+    mbwd()
     torch.cuda.synchronize()
-    f_best, _ = time_events(torch, mp.forward, reps)
-    b_best, _ = time_events(torch, mp.backward, reps)
+    f_best, _ = time_events(torch, mfwd, reps)
+    b_best, _ = time_events(torch, mbwd, reps, mfresh)
     nf = ns.astype(float)
     ffl = float((nf ** 3 / 3 + 2.0 * nf * nf * nb).sum())
     bfl = float((4.0 * nf * nf * nb + 5.0 * nf ** 3 / 3).sum())
@@ -717,13 +783,59 @@ def riccati_workload(torch, _lib, inputs, reps, composed=True):
     return out
 
 
+def compact_line(head, args, restore_bytes, peak_frac, roofline, cpu, per_size, ceil, parity,
+                 single, nxt):
+    """The one stdout line: the headline, the dominant kernel's roofline, the
+    CPU baseline and GFLOP/s against n per routine (best trans case for
+    dgemm), kept short enough to be read whole (about 1.5 KB)."""
+    def best_gemm(n):
+        return max(per_size[f"dgemm_{t}_n{n}"]["gflops"] for t in ("NN", "NT", "TN", "TT"))
+    out = dict(head)
+    out["config"] = {"workload": "dgemm sweep n=%s x4 trans (~1 GiB each) + dpotrf L n=%s x %d"
+                                 % (",".join(map(str, args.gemm_sizes)),
+                                    ",".join(map(str, args.potrf_sizes)), args.potrf_batch),
+                     "potrf_input_copies": args.copies,
+                     "restore_bytes_per_step": restore_bytes}
+    out["fp64_peak_frac"] = peak_frac
+    out["roofline"] = {k: roofline[k] for k in ("bound", "achieved", "peak", "unit", "frac",
+                                                "traffic", "kernel", "avg_launch_ms")}
+    if cpu is not None:
+        out["cpu_baseline"] = {"value": round(cpu["value"], 2), "unit": cpu["unit"],
+                               "cores": cpu["cores"], "kind": "oracle",
+                               "sample": "leading instances of every sweep case, %.0f GFLOP "
+                                         "per case, %.1f s" % (args.cpu_flops_per_case / 1e9,
+                                                               cpu["seconds"]),
+                               "value_1_thread": cpu["value_1_thread"],
+                               "cpu_model": cpu["cpu_model"]}
+    out["gflops_vs_n"] = {
+        "dgemm_best_trans": {str(n): best_gemm(n) for n in args.gemm_sizes},
+        "dpotrf": {str(n): per_size[f"dpotrf_n{n}"]["gflops"] for n in args.potrf_sizes}}
+    out["hbm_ceiling_gbps"] = {k: ceil.get(k) for k in ("hbm_read_gbps", "hbm_copy_gbps",
+                                                        "hbm_3r1w_gbps")}
+    if parity is not None:
+        out["parity"] = {"pass": parity["pass"], "dgemm_max_rel_err": parity["dgemm_max_rel_err"],
+                         "dpotrf_max_residual": parity["dpotrf_max_residual"],
+                         "info_exact": parity["dpotrf_info_exact"]}
+    if single is not None:
+        out["single_call"] = {"kernel": single["kernel"], "rel_err": single["rel_err"],
+                              "latency_us_median": single["latency_us_median"]}
+    if nxt is not None:
+        ub = nxt["uneven_batch"]
+        out["fused_vs_plain"] = {"fused_graph_ms": ub["modes"]["fused_graph"]["best_ms"],
+                                 "speedup": ub["speedup_vs"]}
+    return json.dumps(out, separators=(",", ":"))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--copies", type=int, default=None,
-                    help="pristine dpotrf input copies (default: warmup + steps, at most 12)")
+                    help="pristine dpotrf input copies (default: one per timed step, as many as "
+                         "device memory holds)")
+    ap.add_argument("--details-out", type=str, default=None,
+                    help="also write the full per-size / per-kernel record to this JSON file")
     ap.add_argument("--gemm-sizes", type=str, default=None)
     ap.add_argument("--potrf-sizes", type=str, default=None)
     ap.add_argument("--potrf-batch", type=int, default=None)
@@ -765,7 +877,13 @@ def main():
     args.potrf_sizes = sizes(args.potrf_sizes, inputs.POTRF_SWEEP_SIZES)
     args.potrf_batch = args.potrf_batch or inputs.POTRF_SWEEP_BATCH
     if args.copies is None:
-        args.copies = max(1, min(12, args.warmup + args.steps))
+        # one factored copy per timed step, so that no timed step restores its
+        # input; bounded by what the device holds next to the dgemm operands
+        per_copy = sum(8 * n * n * args.potrf_batch for n in args.potrf_sizes) or 1
+        gemm_bytes = sum(3 * 8 * n * n * inputs.gemm_sweep_batch(n) for n in args.gemm_sizes)
+        total = torch.cuda.get_device_properties(0).total_memory
+        room = total - gemm_bytes - per_copy - (24 << 30)
+        args.copies = max(1, min(args.steps, room // per_copy))
 
     if args.crossover:
         crossover(torch, _lib, inputs, args)
@@ -800,6 +918,10 @@ def main():
     restore = [0]
     for w in range(args.warmup):
         run_step(w, gemm, potrf, _lib, stream, None, restore)
+    # the copies the warmup factored are restored here, outside the timed steps
+    for (n, batch, master, copies, info, _) in potrf:
+        for c in copies[:min(args.warmup, len(copies))]:
+            c.copy_(master)
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} steps)")
 
@@ -808,7 +930,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        run_step(args.warmup + s, gemm, potrf, _lib, stream, timer, restore)
+        run_step(s, gemm, potrf, _lib, stream, timer, restore)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -828,26 +950,28 @@ def main():
     for (n, batch, *_r) in gemm:
         fl, by = gemm_work(n, batch)
         for trans in ("NN", "NT", "TN", "TT"):
-            ms = float(np.mean(durations[("dgemm", trans, n)]))
+            ds = durations[("dgemm", trans, n)]
+            ms = float(np.median(ds))
             kname = f"{_lib.dgemm_kernel_name(trans[0], trans[1], n, n, n)}_{trans}"
             per_size[f"dgemm_{trans}_n{n}"] = {
-                "kernel": kname, "batch": batch, "ms": round(ms, 4),
+                "kernel": kname, "batch": batch, "ms": round(ms, 4), "ms_min": round(min(ds), 4),
                 "gflops": round(fl / ms / 1e6, 1), "gbps": round(by / ms / 1e6, 1),
                 "roof_frac": round((fl / ms / 1e9) / min(PEAK_FP64_TFLOPS,
                                                           fl / by * PEAK_HBM_GBS / 1e3), 3)}
             c = classes.setdefault(kname, {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
-            cnt = len(durations[("dgemm", trans, n)])
-            c["ms"] += ms * cnt
+            cnt = len(ds)
+            c["ms"] += float(np.sum(ds))
             c["launches"] += cnt
             c["flops"] += fl * cnt
             c["bytes"] += by * cnt
             step_flops += fl
     for (n, batch, *_r) in potrf:
         fl, by = potrf_work(n, batch)
-        ms = float(np.mean(durations[("dpotrf", "L", n)]))
+        ds = durations[("dpotrf", "L", n)]
+        ms = float(np.median(ds))
         kname = _lib.dpotrf_kernel_name(n)
         per_size[f"dpotrf_n{n}"] = {
-            "kernel": kname, "batch": batch, "ms": round(ms, 4),
+            "kernel": kname, "batch": batch, "ms": round(ms, 4), "ms_min": round(min(ds), 4),
             "gflops": round(fl / ms / 1e6, 1), "gbps": round(by / ms / 1e6, 1),
             # LAPACK's exact count n^3/3 + n^2/2 + n/6 instead of the paper's n^3/3
             "gflops_lapack_count": round((n ** 3 / 3 + n ** 2 / 2 + n / 6) * batch / ms / 1e6, 1),
@@ -857,8 +981,8 @@ def main():
             "roof_frac": round((fl / ms / 1e9) / min(PEAK_FP64_TFLOPS,
                                                       fl / by * PEAK_HBM_GBS / 1e3), 3)}
         c = classes.setdefault(kname, {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
-        cnt = len(durations[("dpotrf", "L", n)])
-        c["ms"] += ms * cnt
+        cnt = len(ds)
+        c["ms"] += float(np.sum(ds))
         c["launches"] += cnt
         c["flops"] += fl * cnt
         c["bytes"] += by * cnt
@@ -914,7 +1038,10 @@ def main():
             nxt["skinny"] = skinny_sweeps(torch, _lib, inputs, 5)
 
     value = step_flops / (ms_per_step * 1e-3) / 1e9
-    out = {
+    workload = ("square batched dgemm sweep (n in %s, NN/NT/TN/TT, alpha=beta=1, lda=n, batch "
+                "~1 GiB of A+B+C per size) + batched dpotrf L sweep (n in %s, batch %d, one "
+                "non-SPD instance per size)" % (args.gemm_sizes, args.potrf_sizes, args.potrf_batch))
+    head = {
         "metric": METRIC,
         "value": round(value, 1),
         "unit": "GFLOP/s",
@@ -927,11 +1054,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
+    }
+    details = dict(head)
+    details.update({
         "config": {
-            "workload": "square batched dgemm sweep (n in %s, NN/NT/TN/TT, alpha=beta=1, lda=n, "
-                        "batch ~1 GiB of A+B+C per size) + batched dpotrf L sweep (n in %s, "
-                        "batch %d, one non-SPD instance per size)"
-                        % (args.gemm_sizes, args.potrf_sizes, args.potrf_batch),
+            "workload": workload,
             "gemm_sizes": args.gemm_sizes, "potrf_sizes": args.potrf_sizes,
             "potrf_batch": args.potrf_batch, "potrf_input_copies": args.copies,
             "restore_bytes_per_step": restore[0] / args.steps,
@@ -946,8 +1073,16 @@ def main():
         "parity": parity,
         "single_call": single,
         "next": nxt,
-    }
-    print(json.dumps(out), flush=True)
+    })
+    blob = json.dumps(details)
+    if args.details_out:
+        with open(args.details_out, "w") as f:
+            f.write(blob + "\n")
+    print(f"[bench] details {blob}", file=sys.stderr, flush=True)
+
+    line = compact_line(head, args, restore[0] / args.steps, details["fp64_peak_frac"], roofline,
+                        cpu, per_size, ceil, parity, single, nxt)
+    print(line, flush=True)
 
 
 if __name__ == "__main__":

@@ -488,6 +488,24 @@ int mb_riccati_workspace_size(int nx, int nu, int batch, size_t *bytes);
 int mb_ceiling_fp64(int kind, int blocks, int iters, double *out, double *flops,
                     hipStream_t stream);
 
+/*
+ * Measured HBM ceiling (roofline support; not part of the BLAS path).  One
+ * streaming launch on `stream` over device buffers the caller owns, with
+ * 16-byte non-temporal loads and stores and four loads in flight per thread:
+ * kind 0 = read src[0, n) (one double per thread of the grid is stored to
+ * `out`, blocks * 256 doubles), kind 1 = copy dst[0, n) = src[0, n), kind 2 =
+ * three reads per write, dst[i] = src[i] + src[n + i] + src[2n + i] (src
+ * holds 3n doubles).  `blocks` workgroups of 256 threads walk the buffer with
+ * a grid stride.  *bytes (host) receives the bytes the launch must move
+ * (8n, 16n, 32n); the caller times it.  Buffers must not overlap and must be
+ * 16-byte aligned (torch allocations are).
+ * Arguments: kind 1, src 2, dst (unused for kind 0) 3, n (> 0, even) 4,
+ * blocks 5, out (kind 0) 6, bytes 7 (illegal -> -position); MB_ERR_HIP on a
+ * launch failure.
+ */
+int mb_ceiling_hbm(int kind, const double *src, double *dst, int64_t n, int blocks, double *out,
+                   double *bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------- misc --- */
 
 /* Static text for a status code (never NULL). */

@@ -36,7 +36,7 @@ EXPORTS = (
     "mb_dgemm_", "mb_dpotrf_",
     "mb_dtrmm_rlnn_strided_batched", "mb_dsyrk_ln_strided_batched",
     "mb_riccati_strided_batched", "mb_riccati_workspace_size",
-    "mb_ceiling_fp64",
+    "mb_ceiling_fp64", "mb_ceiling_hbm",
     "mb_status_string", "mb_version",
 )
 
@@ -104,6 +104,7 @@ def _load():
     lib.mb_dpotrf_kernel_name.argtypes = [c_int]
     lib.mb_version.argtypes = []
     lib.mb_ceiling_fp64.argtypes = [c_int, c_int, c_int, vp, vp, vp]
+    lib.mb_ceiling_hbm.argtypes = [c_int, vp, vp, c_i64, c_int, vp, vp, vp]
     lib.mb_dgemm_backward_strided_batched.argtypes = [
         c_char, c_char, c_int, c_int, c_int, c_double, vp, c_int, c_i64, vp, c_int, c_i64,
         vp, c_int, c_i64, vp, c_int, c_i64, vp, c_int, c_i64, c_int, vp]
@@ -299,6 +300,14 @@ def ceiling_fp64(kind, blocks, iters, out, stream=0):
     fl = ctypes.c_double(0.0)
     st = lib.mb_ceiling_fp64(kind, blocks, iters, out, ctypes.byref(fl), stream)
     return st, fl.value
+
+
+def ceiling_hbm(kind, src, dst, n, blocks, out, stream=0):
+    """(status, bytes) of one launch of mb_ceiling_hbm (kind 0 read, 1 copy,
+    2 three reads per write)."""
+    by = ctypes.c_double(0.0)
+    st = lib.mb_ceiling_hbm(kind, src, dst, n, blocks, out, ctypes.byref(by), stream)
+    return st, by.value
 
 
 def problems_array(problems):

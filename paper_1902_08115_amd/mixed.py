@@ -10,6 +10,13 @@ fused plan (one persistent kernel launch through a HIP graph).
 Every operand lives in one flat FP64 device arena per role, instance after
 instance, tight leading dimensions; ``view(role, b)`` returns instance b as a
 (rows, cols) column-major view.
+
+Calling the object, ``C = mp(A, B)`` with A and B flat arenas of that layout,
+runs the forward through a ``torch.autograd.Function``; ``C.backward(Cbar)``
+(or any loss built on C) then runs the backward plans, and A.grad, B.grad
+receive Abar and Bbar.  C is a view of the object's own C arena, as the
+output of a captured graph is: the next forward overwrites it, and a
+backward whose forward has been overwritten raises.
 """
 from __future__ import annotations
 
@@ -61,6 +68,29 @@ class MixedCholeskyProduct:
         self.plans = {name: blas.Plan(pr) for name, pr in (("potrf", potrf), ("laset", laset),
                                                            ("gemm", gemm), ("gemm_b", gemm_b),
                                                            ("adjoint", adj))}
+        self.forwards = 0  # forward count: a backward must follow its own forward
+
+    def __call__(self, A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
+        """C = chol(A) B for flat arenas A (sum n_b^2) and B (sum n_b nb),
+        differentiable in both (symmetric gradient for A)."""
+        return _MixedCholeskyProductFn.apply(A, B, self)
+
+    def load(self, role: str, X: torch.Tensor):
+        """Copy X into the role's arena (nothing to do if X is the arena)."""
+        dst = self.buf[role]
+        if X.dtype != torch.float64 or X.device != dst.device or X.numel() != dst.numel():
+            raise ValueError(f"{role}: expected {dst.numel()} float64 values on {dst.device}")
+        if X.data_ptr() != dst.data_ptr():
+            dst.copy_(X.reshape(-1))
+
+    def symmetrize_index(self) -> torch.Tensor:
+        """Index t with X[t] = instance-wise transpose of the A-shaped arena X."""
+        parts = []
+        for b, n in enumerate(self.ns.tolist()):
+            j, i = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")  # element i + j n
+            parts.append(int(self.off_sq[b]) + (j + i * n).ravel())
+        idx = np.concatenate(parts) if parts else np.zeros(0, dtype=np.int64)
+        return torch.from_numpy(idx.astype(np.int64)).to(self.buf["A"].device)
 
     def view(self, role: str, b: int) -> torch.Tensor:
         n = int(self.ns[b])
@@ -74,6 +104,7 @@ class MixedCholeskyProduct:
         self.buf["L"].copy_(self.buf["A"])
         for name in ("potrf", "laset", "gemm"):
             self.plans[name].execute(mode, stream)
+        self.forwards += 1
 
     def backward(self, mode=None, stream=None):
         for name in ("gemm_b", "adjoint"):
@@ -83,3 +114,27 @@ class MixedCholeskyProduct:
         for p in self.plans.values():
             p.close()
         self.plans = {}
+
+
+class _MixedCholeskyProductFn(torch.autograd.Function):
+    """Forward and backward plans of a MixedCholeskyProduct behind autograd."""
+
+    @staticmethod
+    def forward(ctx, A, B, mp):
+        mp.load("A", A)
+        mp.load("B", B)
+        mp.forward()
+        ctx.mp, ctx.version = mp, mp.forwards
+        return mp.buf["C"].view(-1)
+
+    @staticmethod
+    def backward(ctx, Cbar):
+        mp = ctx.mp
+        if mp.forwards != ctx.version:
+            raise RuntimeError("MixedCholeskyProduct: a later forward overwrote the factors "
+                               "this backward needs")
+        mp.load("Cbar", Cbar.contiguous())
+        mp.backward()
+        gA = mp.buf["Abar"].clone() if ctx.needs_input_grad[0] else None
+        gB = mp.buf["Bbar"].clone() if ctx.needs_input_grad[1] else None
+        return gA, gB, None

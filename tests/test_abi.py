@@ -371,6 +371,23 @@ def test_ceiling_probe_argument_errors(L):
     assert L.lib.mb_ceiling_fp64(0, 1, 1, buf, None, None) == -5
 
 
+def test_hbm_ceiling_probe_argument_errors(L):
+    """mb_ceiling_hbm validates every argument (its position) before launching."""
+    import ctypes
+    by = ctypes.c_double(0.0)
+    pb = ctypes.byref(by)
+    buf = ctypes.c_void_p(16)  # never dereferenced: every call below fails its checks first
+    assert L.lib.mb_ceiling_hbm(3, buf, buf, 2, 1, buf, pb, None) == -1
+    assert L.lib.mb_ceiling_hbm(0, None, buf, 2, 1, buf, pb, None) == -2
+    assert L.lib.mb_ceiling_hbm(1, buf, None, 2, 1, buf, pb, None) == -3
+    assert L.lib.mb_ceiling_hbm(2, buf, None, 2, 1, buf, pb, None) == -3
+    assert L.lib.mb_ceiling_hbm(1, buf, buf, 0, 1, buf, pb, None) == -4
+    assert L.lib.mb_ceiling_hbm(1, buf, buf, 3, 1, buf, pb, None) == -4
+    assert L.lib.mb_ceiling_hbm(1, buf, buf, 2, 0, buf, pb, None) == -5
+    assert L.lib.mb_ceiling_hbm(0, buf, None, 2, 1, None, pb, None) == -6
+    assert L.lib.mb_ceiling_hbm(0, buf, None, 2, 1, buf, None, None) == -7
+
+
 def test_tuned_tables_parse_and_tiny_dispatch(L):
     """The committed dispatch tables parse back (the autotuner keeps their
     choices within its noise margin) and re-emit byte for byte; results of at

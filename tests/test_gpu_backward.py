@@ -32,40 +32,59 @@ def _factor_host(A, n, ld):
     return L
 
 
+def _spread(blocks, ld, stride):
+    """Flat buffer holding instance b's (n, ld) column-major block at b*stride,
+    NaN in the gaps between instances."""
+    batch, n = blocks.shape[0], blocks.shape[1]
+    flat = np.full((batch - 1) * stride + n * ld, np.nan)
+    for b in range(batch):
+        flat[b * stride:b * stride + n * ld] = blocks[b].ravel()
+    return flat
+
+
 @pytest.mark.parametrize("n", [1, 2, 5, 15, 16, 17, 31, 33, 47, 64, 100, 129, 160, 192, 256, 304])
 def test_cholesky_adjoint_vs_oracle(n):
     """Abar for random lower Lbar at orders spanning ragged tiles, one tile,
     many tiles and the 304 limit: within 1e-9 of the oracle adjoint (expected
     ~1e-14), exactly symmetric, the strict upper parts of L and Lbar (NaN)
-    never read, the leading-dimension padding of Abar untouched."""
+    never read, the leading-dimension padding of Abar and the gaps between
+    its instances untouched.  L, Lbar and Abar each have their own leading
+    dimension and instance stride, with NaN between instances, so an ld or
+    stride taken from the wrong operand reads NaN or writes out of place."""
     torch, _lib, _ = torch_mods()
     g = inputs.rng(inputs.seed_for(4, n))
     batch = 6 if n <= 64 else 3
-    ld = n + 3
-    A = inputs.spd_batch(g, batch, n, ld=ld)
-    L = _factor_host(A, n, ld)
-    Lb = inputs.colmajor(g, batch, n, n, ld)
+    ldl, ldlb, ldab = n + 3, n + 1, n + 6
+    sl, slb, sab = n * ldl + 5, n * ldlb + 17, n * ldab + 2
+    A = inputs.spd_batch(g, batch, n, ld=ldl)
+    L = _factor_host(A, n, ldl)
+    Lb = inputs.colmajor(g, batch, n, n, ldlb)
     iu = np.triu_indices(n, 1)
     Lb[:, iu[1], iu[0]] = np.nan
-    ref = np.full((batch, n, ld), np.nan)
     Lh = np.where(np.isnan(L), 0.0, L)
     Lbh = np.where(np.isnan(Lb), 0.0, Lb)
-    oracle.dpotrf_l_adjoint_strided_batched(n, Lh.ravel(), ld, n * ld, Lbh.ravel(), ld, n * ld,
-                                            ref.ravel(), ld, n * ld, batch)
+    ref = _spread(np.full((batch, n, ldab), np.nan), ldab, sab)
+    oracle.dpotrf_l_adjoint_strided_batched(n, _spread(Lh, ldl, sl), ldl, sl,
+                                            _spread(Lbh, ldlb, slb), ldlb, slb, ref, ldab, sab,
+                                            batch)
     say(f"cholesky adjoint n={n} batch={batch}")
-    dL, dLb = dev(L), dev(Lb)
-    dAb = dev(np.full((batch, n, ld), np.nan))
-    st = _lib.dpotrf_l_backward_strided_batched(n, dL.data_ptr(), ld, n * ld, dLb.data_ptr(), ld,
-                                                n * ld, dAb.data_ptr(), ld, n * ld, batch,
+    dL, dLb = dev(_spread(L, ldl, sl)), dev(_spread(Lb, ldlb, slb))
+    dAb = dev(_spread(np.full((batch, n, ldab), np.nan), ldab, sab))
+    st = _lib.dpotrf_l_backward_strided_batched(n, dL.data_ptr(), ldl, sl, dLb.data_ptr(), ldlb,
+                                                slb, dAb.data_ptr(), ldab, sab, batch,
                                                 torch.cuda.current_stream().cuda_stream)
     assert st == 0, st
-    G = host(dAb).reshape(batch, n, ld)
+    G = host(dAb)
     for b in range(batch):
-        g2, r2 = G[b].T[:n], ref[b].T[:n]
+        blk = G[b * sab:b * sab + n * ldab].reshape(n, ldab)
+        rblk = ref[b * sab:b * sab + n * ldab].reshape(n, ldab)
+        g2, r2 = blk.T[:n], rblk.T[:n]
         assert np.isfinite(g2).all(), b
         assert rel(g2, r2) <= GRAD_TOL, (b, rel(g2, r2))
         assert np.array_equal(g2, g2.T), b
-        assert np.isnan(G[b].T[n:]).all(), "padding touched"
+        assert np.isnan(blk.T[n:]).all(), "padding touched"
+        if b + 1 < batch:
+            assert np.isnan(G[b * sab + n * ldab:(b + 1) * sab]).all(), "gap touched"
 
 
 def test_cholesky_adjoint_pointer_array_and_zero_sizes():
@@ -240,9 +259,12 @@ def test_cholesky_raises_on_non_spd():
 
 def test_mixed_orders_fused_plans():
     """The mixed batch (2048 instances, n = floor(exp(U[ln 16, ln 193)))),
-    forward and backward as fused plans: 64 sampled instances match the
-    oracle forward and gradient, and central differences along 5 directions
-    match the directional derivative."""
+    forward and backward as fused plans behind a torch.autograd.Function:
+    64 sampled instances match the oracle forward and gradient (1e-9), and
+    central differences (h = 1e-6) along 50 random directions (dA symmetric
+    per instance, dB uniform) match the directional derivative of
+    <Cbar, C> that autograd's gradients give; a backward whose forward was
+    overwritten raises."""
     torch, _lib, blas = torch_mods()
     from paper_1902_08115_amd.mixed import MixedCholeskyProduct
     ns = inputs.backward_mixed_sizes(inputs.seed_for(4, 10))
@@ -250,23 +272,32 @@ def test_mixed_orders_fused_plans():
     mp = MixedCholeskyProduct(ns, nb)
     g = inputs.rng(inputs.seed_for(4, 11))
     # inputs: SPD A per instance, B and the cotangent W uniform [-1, 1)
+    A0 = torch.zeros_like(mp.buf["A"])
     for n in np.unique(ns):
         idx = np.nonzero(ns == n)[0]
         S = inputs.torch_spd(len(idx), int(n), seed=inputs.seed_for(4, 20000 + int(n)))
         for j, b in enumerate(idx):
-            mp.view("A", int(b)).copy_(S[j])
-    mp.buf["B"].uniform_(-1.0, 1.0, generator=torch.Generator(device="cuda").manual_seed(12))
-    mp.buf["Cbar"].uniform_(-1.0, 1.0, generator=torch.Generator(device="cuda").manual_seed(13))
-    say(f"mixed plans: {len(ns)} instances, n {ns.min()}..{ns.max()}")
-    mp.forward()
-    mp.backward()
+            o = int(mp.off_sq[b])
+            A0[o:o + int(n) * int(n)].view(int(n), int(n)).t().copy_(S[j])
+    B0 = torch.empty_like(mp.buf["B"]).uniform_(
+        -1.0, 1.0, generator=torch.Generator(device="cuda").manual_seed(12))
+    W = torch.empty_like(mp.buf["C"]).uniform_(
+        -1.0, 1.0, generator=torch.Generator(device="cuda").manual_seed(13))
+    say(f"mixed plans through autograd: {len(ns)} instances, n {ns.min()}..{ns.max()}")
+    A = A0.clone().requires_grad_(True)
+    B = B0.clone().requires_grad_(True)
+    C = mp(A, B)
+    (C * W).sum().backward()
     torch.cuda.synchronize()
     assert int(mp.info.abs().sum()) == 0
+    Abar, Bbar = A.grad.detach().clone(), B.grad.detach().clone()
+    Cg = C.detach().clone()
     for b in sorted(g.choice(len(ns), 64, replace=False)):
         n = int(ns[b])
-        a = np.asfortranarray(mp.view("A", b).cpu().numpy())
-        bm = np.asfortranarray(mp.view("B", b).cpu().numpy())
-        w = np.asfortranarray(mp.view("Cbar", b).cpu().numpy())
+        o, r = int(mp.off_sq[b]), int(mp.off_rect[b])
+        a = A0[o:o + n * n].view(n, n).t().cpu().numpy().copy(order="F")
+        bm = B0[r:r + n * nb].view(nb, n).t().cpu().numpy().copy(order="F")
+        w = W[r:r + n * nb].view(nb, n).t().cpu().numpy().copy(order="F")
         L = a.copy(order="F")
         assert oracle.dpotrf_l(L) == 0
         L = np.asfortranarray(np.tril(L))
@@ -274,36 +305,33 @@ def test_mixed_orders_fused_plans():
         oracle.dgemm("N", "N", 1.0, L, bm, 0.0, Cref)
         Lbar = np.zeros((n, n), order="F")
         oracle.dgemm("N", "T", 1.0, w, bm, 0.0, Lbar)
-        Bbar = np.zeros((n, nb), order="F")
-        oracle.dgemm("T", "N", 1.0, L, w, 0.0, Bbar)
-        Abar = oracle.dpotrf_l_adjoint(L, Lbar)
-        assert rel(mp.view("C", b).cpu().numpy(), Cref) <= GEMM_TOL, b
-        assert rel(mp.view("Abar", b).cpu().numpy(), Abar) <= GRAD_TOL, b
-        assert rel(mp.view("Bbar", b).cpu().numpy(), Bbar) <= GRAD_TOL, b
-    # finite differences of <Cbar, C> over the whole batch
-    A0, B0 = mp.buf["A"].clone(), mp.buf["B"].clone()
-    Abar, Bbar = mp.buf["Abar"].clone(), mp.buf["Bbar"].clone()
+        Bref = np.zeros((n, nb), order="F")
+        oracle.dgemm("T", "N", 1.0, L, w, 0.0, Bref)
+        Aref = oracle.dpotrf_l_adjoint(L, Lbar)
+        assert rel(Cg[r:r + n * nb].view(nb, n).t().cpu().numpy(), Cref) <= GEMM_TOL, b
+        assert rel(Abar[o:o + n * n].view(n, n).t().cpu().numpy(), Aref) <= GRAD_TOL, b
+        assert rel(Bbar[r:r + n * nb].view(nb, n).t().cpu().numpy(), Bref) <= GRAD_TOL, b
+    # a second forward overwrites the factors the first graph's backward needs
+    C1 = mp(A, B)
+    C2 = mp(A, B)
+    with pytest.raises(RuntimeError, match="overwrote"):
+        (C1 * W).sum().backward()
+    del C2
+    # central differences of <W, C> over the whole batch, 50 directions
+    t = mp.symmetrize_index()
     h = inputs.FD_STEP
+    with torch.no_grad():
+        def f(Ax, Bx):
+            return float((mp(Ax, Bx) * W).sum())
 
-    def f():
-        mp.forward()
-        return float((mp.buf["C"] * mp.buf["Cbar"]).sum())
-
-    for d in range(5):
-        gen = torch.Generator(device="cuda").manual_seed(300 + d)
-        dA = torch.empty_like(A0).uniform_(-1.0, 1.0, generator=gen)
-        for b in range(len(ns)):  # symmetric per instance
-            o, n = int(mp.off_sq[b]), int(ns[b])
-            blk = dA[o:o + n * n].view(n, n)
-            blk.copy_(0.5 * (blk + blk.t()))
-        dB = torch.empty_like(B0).uniform_(-1.0, 1.0, generator=gen)
-        mp.buf["A"].copy_(A0 + h * dA)
-        mp.buf["B"].copy_(B0 + h * dB)
-        fp = f()
-        mp.buf["A"].copy_(A0 - h * dA)
-        mp.buf["B"].copy_(B0 - h * dB)
-        fm = f()
-        fd = (fp - fm) / (2 * h)
-        an = float((Abar * dA).sum() + (Bbar * dB).sum())
-        assert abs(fd - an) <= FD_TOL * abs(fd), (d, fd, an)
+        for d in range(inputs.FD_DIRECTIONS):
+            gen = torch.Generator(device="cuda").manual_seed(300 + d)
+            dA = torch.empty_like(A0).uniform_(-1.0, 1.0, generator=gen)
+            dA = 0.5 * (dA + dA[t])  # symmetric per instance
+            dB = torch.empty_like(B0).uniform_(-1.0, 1.0, generator=gen)
+            fp = f(A0 + h * dA, B0 + h * dB)
+            fm = f(A0 - h * dA, B0 - h * dB)
+            fd = (fp - fm) / (2 * h)
+            an = float((Abar * dA).sum() + (Bbar * dB).sum())
+            assert abs(fd - an) <= FD_TOL * abs(fd), (d, fd, an)
     mp.close()

@@ -54,11 +54,12 @@ def test_sweep_sizes_with_failing_instance(si, n):
         assert d <= POTRF_TOL, d
 
 
-@pytest.mark.parametrize("n", [1, 2, 5, 15, 16, 17, 31, 33, 47, 64, 65, 100, 129, 200, 256, 272,
-                               288, 300])
+@pytest.mark.parametrize("n", [1, 2, 5, 15, 16, 17, 31, 33, 47, 64, 65, 90, 100, 128, 129, 150, 176,
+                               185, 200, 224, 237, 256, 272, 288, 300, 304])
 def test_exact_integer_factor(n):
     """A = L0 L0^T with integer L0 (diagonal in {1,2,4}): the factor is L0
-    exactly for any evaluation order, so the GPU result must match bit for bit."""
+    exactly for any evaluation order, so the GPU result must match bit for bit.
+    The orders reach every tile count 1..19 (each its own kernel instance)."""
     g = inputs.rng(8000 + n)
     batch = 3
     A = np.full((batch, n, n + 1), np.nan)
@@ -73,6 +74,35 @@ def test_exact_integer_factor(n):
     assert (info == 0).all()
     for b in range(batch):
         assert np.array_equal(np.tril(Ag[b].T[:n, :n]), L0s[b]), f"instance {b}"
+
+
+@pytest.mark.parametrize("n", [144, 240])
+def test_info_in_pipelined_orders(n):
+    """Orders with the pipelined loops and the LDS pivot cache: a_jj = -1 in
+    the first and second diagonal tile of the first pair, in both tiles of a
+    later pair, inside the first panel rows' range and in the last column.
+    info is j+1 and the columns before j match the oracle's partial factor."""
+    import oracle
+    cols = [3, 16 + 5, 16 * 6 + 3, 16 * 7 + 9, 16 * 4, n - 1]
+    g = inputs.rng(8150 + n)
+    batch = len(cols) + 1
+    A = inputs.spd_batch(g, batch, n, ld=n + 2, upper_value=np.nan)
+    for b, j in enumerate(cols):
+        A[b, j, j] = -1.0
+    say(f"dpotrf info pipelined n={n} cols={cols}")
+    Ag, info = _run(n, A, batch)
+    assert list(info) == [j + 1 for j in cols] + [0], info
+    for b, j in enumerate(cols):
+        Lr = np.ascontiguousarray(A[b:b + 1]).ravel().copy()
+        assert oracle.dpotrf_l_raw(n, Lr, n + 2) == j + 1
+        if j == 0:
+            continue
+        Lr = Lr.reshape(A[b:b + 1].shape)[0].T[:n, :j]
+        Lg = Ag[b].T[:n, :j]
+        low = np.tril(np.ones((n, j), dtype=bool))
+        d = np.linalg.norm((Lg - Lr)[low]) / np.linalg.norm(Lr[low])
+        assert d <= POTRF_TOL, (j, d)
+        assert np.isnan(Ag[b].T[:n, :n][np.triu_indices(n, 1)]).all(), "upper touched"
 
 
 def test_info_closed_form_every_column():
