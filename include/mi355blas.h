@@ -57,6 +57,7 @@ extern "C" {
 #define MB_ERR_HIP (-1000)
 #define MB_ERR_UNSUPPORTED (-1001)
 #define MB_ERR_INVALID_PROBLEM (-1002) /* a plan problem failed validation */
+#define MB_ERR_SCRATCH (-1003) /* more device scratch than the allocation-free entry point holds */
 
 /* Kernel family selection for the *_ex calls. */
 #define MB_VARIANT_AUTO 0   /* measured size switch (what the plain calls use) */
@@ -463,6 +464,34 @@ int mb_riccati_strided_batched(int nx, int nu, int N, const double *BAt, int ldb
                                int64_t strideQ, double *F, int ldf, int64_t stageF,
                                int64_t strideF, double *LN, int ldl, int64_t strideL, int *info,
                                void *work, size_t work_bytes, int batch, hipStream_t stream);
+
+/*
+ * Allocation-free variant of mb_riccati_strided_batched, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops
+ * that forbid hipMalloc): the same recursion, results bit-identical to
+ * mb_riccati_strided_batched, but the workspace slots come from a device
+ * scratch array inside the library (64 MiB per device, held from the first
+ * load of the library until the process ends) instead of a caller's buffer.
+ * The call allocates nothing and never synchronizes.  The kernel's waves are
+ * limited to the slots that fit in the scratch (64 MiB / the slot size of
+ * mb_riccati_strided_batched), so shapes whose C does not stay on chip run
+ * with fewer concurrent waves than a full-occupancy workspace allows.
+ * Every call on one device shares that device's scratch: calls that overlap
+ * in time on one device (different streams, different host threads) race;
+ * calls ordered on one stream are safe, and nothing needs clearing between
+ * them.  A shape whose single slot exceeds the scratch returns MB_ERR_SCRATCH
+ * (no shape with nu + nx <= 304 does: the largest slot is 722 KiB).
+ * Arguments and positions are those of mb_riccati_strided_batched without
+ * work and work_bytes: batch is argument 23, stream 24.  MB_ERR_HIP when the
+ * scratch address cannot be resolved or the launch fails.
+ */
+int mb_riccati_strided_batched_noalloc(int nx, int nu, int N, const double *BAt, int ldbat,
+                                       int64_t stageBAt, int64_t strideBAt, const double *RSQ,
+                                       int ldrsq, int64_t stageRSQ, int64_t strideRSQ,
+                                       const double *QN, int ldq, int64_t strideQ, double *F,
+                                       int ldf, int64_t stageF, int64_t strideF, double *LN,
+                                       int ldl, int64_t strideL, int *info, int batch,
+                                       hipStream_t stream);
 
 /*
  * Workspace bytes for mb_riccati_strided_batched at full occupancy of the

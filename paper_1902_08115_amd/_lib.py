@@ -16,6 +16,7 @@ MB_OK = 0
 MB_ERR_HIP = -1000
 MB_ERR_UNSUPPORTED = -1001
 MB_ERR_INVALID_PROBLEM = -1002
+MB_ERR_SCRATCH = -1003
 VARIANT_AUTO, VARIANT_DIRECT, VARIANT_PACKED, VARIANT_REGTILE = 0, 1, 2, 3
 OP_DGEMM, OP_DPOTRF, OP_DPOTRF_ADJOINT, OP_DLASET = 0, 1, 2, 3
 PLAN_FUSED_GRAPH, PLAN_FUSED, PLAN_GROUPED, PLAN_GROUPED_GRAPH = 0, 1, 2, 3
@@ -35,7 +36,8 @@ EXPORTS = (
     "mb_plan_destroy",
     "mb_dgemm_", "mb_dpotrf_",
     "mb_dtrmm_rlnn_strided_batched", "mb_dsyrk_ln_strided_batched",
-    "mb_riccati_strided_batched", "mb_riccati_workspace_size",
+    "mb_riccati_strided_batched", "mb_riccati_strided_batched_noalloc",
+    "mb_riccati_workspace_size",
     "mb_ceiling_fp64", "mb_ceiling_hbm",
     "mb_status_string", "mb_version",
 )
@@ -132,6 +134,9 @@ def _load():
     lib.mb_riccati_strided_batched.argtypes = [
         c_int, c_int, c_int, vp, c_int, c_i64, c_i64, vp, c_int, c_i64, c_i64, vp, c_int, c_i64,
         vp, c_int, c_i64, c_i64, vp, c_int, c_i64, vp, vp, ctypes.c_size_t, c_int, vp]
+    lib.mb_riccati_strided_batched_noalloc.argtypes = [
+        c_int, c_int, c_int, vp, c_int, c_i64, c_i64, vp, c_int, c_i64, c_i64, vp, c_int, c_i64,
+        vp, c_int, c_i64, c_i64, vp, c_int, c_i64, vp, c_int, vp]
     lib.mb_riccati_workspace_size.argtypes = [c_int, c_int, c_int, ctypes.POINTER(ctypes.c_size_t)]
     for name in EXPORTS:
         getattr(lib, name).restype = ctypes.c_char_p if name in _STRING_FNS else c_int
@@ -282,6 +287,14 @@ def riccati_strided_batched(nx, nu, N, BAt, ldbat, stBAt, sBAt, RSQ, ldrsq, stRS
     return lib.mb_riccati_strided_batched(nx, nu, N, BAt, ldbat, stBAt, sBAt, RSQ, ldrsq, stRSQ,
                                           sRSQ, QN, ldq, sQ, F, ldf, stF, sF, LN, ldl, sL, info,
                                           work, work_bytes, batch, stream)
+
+
+def riccati_strided_batched_noalloc(nx, nu, N, BAt, ldbat, stBAt, sBAt, RSQ, ldrsq, stRSQ, sRSQ,
+                                    QN, ldq, sQ, F, ldf, stF, sF, LN, ldl, sL, info, batch,
+                                    stream=0) -> int:
+    return lib.mb_riccati_strided_batched_noalloc(nx, nu, N, BAt, ldbat, stBAt, sBAt, RSQ, ldrsq,
+                                                  stRSQ, sRSQ, QN, ldq, sQ, F, ldf, stF, sF, LN,
+                                                  ldl, sL, info, batch, stream)
 
 
 def riccati_workspace_size(nx, nu, batch):

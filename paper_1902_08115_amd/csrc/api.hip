@@ -227,6 +227,76 @@ int run_potrf(PotrfArgs &a, hipStream_t s)
 
 }  // namespace mb
 
+// Shared by the workspace and the allocation-free Riccati entry points; with
+// noalloc the workspace is the library's device scratch and batch is
+// argument 23 (work and work_bytes are not in that argument list).
+static int riccati_call(int nx, int nu, int N, const double *BAt, int ldbat, int64_t stageBAt,
+                        int64_t strideBAt, const double *RSQ, int ldrsq, int64_t stageRSQ,
+                        int64_t strideRSQ, const double *QN, int ldq, int64_t strideQ, double *F,
+                        int ldf, int64_t stageF, int64_t strideF, double *LN, int ldl,
+                        int64_t strideL, int *info, void *work, size_t work_bytes, int batch,
+                        hipStream_t stream, bool noalloc)
+{
+    const int m = nx + nu;
+    const int64_t span_f = m > 0 ? (int64_t)ldf * (m - 1) + m : 0;
+    if (nx < 0) return -1;
+    if (nu < 0) return -2;
+    if (N < 0) return -3;
+    if (ldbat < std::max(1, m)) return -5;
+    if (stageBAt < 0) return -6;
+    if (strideBAt < 0) return -7;
+    if (ldrsq < std::max(1, m)) return -9;
+    if (stageRSQ < 0) return -10;
+    if (strideRSQ < 0) return -11;
+    if (ldq < std::max(1, nx)) return -13;
+    if (strideQ < 0) return -14;
+    if (ldf < std::max(1, m)) return -16;
+    if (stageF < 0 || (N > 1 && stageF < span_f)) return -17;
+    if (strideF < 0 || (batch > 1 && N > 0 && strideF < (int64_t)(N - 1) * stageF + span_f))
+        return -18;
+    if (ldl < std::max(1, nx)) return -20;
+    if (strideL < 0 || (batch > 1 && nx > 0 && strideL < (int64_t)ldl * (nx - 1) + nx))
+        return -21;
+    if (batch < 0) return noalloc ? -23 : -25;
+    if (m > mb::POTRF_MAX_N) return MB_ERR_UNSUPPORTED;
+    if (batch == 0)
+        return MB_OK;
+    if (!BAt && N > 0 && m > 0 && nx > 0) return -4;
+    if (!RSQ && N > 0 && m > 0) return -8;
+    if (!QN && nx > 0) return -12;
+    if (!F && N > 0 && m > 0) return -15;
+    if (!LN && nx > 0) return -19;
+    if (!info) return -22;
+    const int64_t slot = mb::riccati_slot_doubles(nx, nu);
+    if (noalloc && slot > 0) {
+        // the file-scope device scratch stands in for the caller's workspace
+        const hipError_t se = mb::riccati_scratch(&work, &work_bytes);
+        if (se != hipSuccess)
+            return MB_ERR_HIP;
+        if ((size_t)slot * sizeof(double) > work_bytes)
+            return MB_ERR_SCRATCH;
+    }
+    const int64_t slots = slot > 0 ? (int64_t)(work_bytes / ((size_t)slot * sizeof(double))) : batch;
+    if (slot > 0 && !work) return -23;
+    if (slots < 1) return -24;
+    int waves = 0;
+    hipError_t e = mb::riccati_max_waves(nx, nu, &waves);
+    if (e != hipSuccess)
+        return MB_ERR_HIP;
+    waves = (int)std::min<int64_t>(std::min<int64_t>(waves, slots), batch);
+    mb::RiccatiArgs a{};
+    a.nx = nx; a.nu = nu; a.N = N;
+    a.BAt = BAt; a.stBAt = stageBAt; a.sBAt = strideBAt; a.ldbat = ldbat;
+    a.RSQ = RSQ; a.stRSQ = stageRSQ; a.sRSQ = strideRSQ; a.ldrsq = ldrsq;
+    a.QN = QN; a.sQ = strideQ; a.ldq = ldq;
+    a.F = F; a.stF = stageF; a.sF = strideF; a.ldf = ldf;
+    a.LN = LN; a.sL = strideL; a.ldl = ldl;
+    a.info = info;
+    a.work = (double *)work;
+    a.batch = batch;
+    return to_status(mb::launch_riccati(a, waves, stream));
+}
+
 extern "C" {
 
 int mb_dgemm(char transa, char transb, int m, int n, int k, double alpha, const double *A,
@@ -660,56 +730,22 @@ int mb_riccati_strided_batched(int nx, int nu, int N, const double *BAt, int ldb
                                int64_t strideF, double *LN, int ldl, int64_t strideL, int *info,
                                void *work, size_t work_bytes, int batch, hipStream_t stream)
 {
-    const int m = nx + nu;
-    const int64_t span_f = m > 0 ? (int64_t)ldf * (m - 1) + m : 0;
-    if (nx < 0) return -1;
-    if (nu < 0) return -2;
-    if (N < 0) return -3;
-    if (ldbat < std::max(1, m)) return -5;
-    if (stageBAt < 0) return -6;
-    if (strideBAt < 0) return -7;
-    if (ldrsq < std::max(1, m)) return -9;
-    if (stageRSQ < 0) return -10;
-    if (strideRSQ < 0) return -11;
-    if (ldq < std::max(1, nx)) return -13;
-    if (strideQ < 0) return -14;
-    if (ldf < std::max(1, m)) return -16;
-    if (stageF < 0 || (N > 1 && stageF < span_f)) return -17;
-    if (strideF < 0 || (batch > 1 && N > 0 && strideF < (int64_t)(N - 1) * stageF + span_f))
-        return -18;
-    if (ldl < std::max(1, nx)) return -20;
-    if (strideL < 0 || (batch > 1 && nx > 0 && strideL < (int64_t)ldl * (nx - 1) + nx))
-        return -21;
-    if (batch < 0) return -25;
-    if (m > mb::POTRF_MAX_N) return MB_ERR_UNSUPPORTED;
-    if (batch == 0)
-        return MB_OK;
-    if (!BAt && N > 0 && m > 0 && nx > 0) return -4;
-    if (!RSQ && N > 0 && m > 0) return -8;
-    if (!QN && nx > 0) return -12;
-    if (!F && N > 0 && m > 0) return -15;
-    if (!LN && nx > 0) return -19;
-    if (!info) return -22;
-    const int64_t slot = mb::riccati_slot_doubles(nx, nu);
-    const int64_t slots = slot > 0 ? (int64_t)(work_bytes / ((size_t)slot * sizeof(double))) : batch;
-    if (slot > 0 && !work) return -23;
-    if (slots < 1) return -24;
-    int waves = 0;
-    hipError_t e = mb::riccati_max_waves(nx, nu, &waves);
-    if (e != hipSuccess)
-        return MB_ERR_HIP;
-    waves = (int)std::min<int64_t>(std::min<int64_t>(waves, slots), batch);
-    mb::RiccatiArgs a{};
-    a.nx = nx; a.nu = nu; a.N = N;
-    a.BAt = BAt; a.stBAt = stageBAt; a.sBAt = strideBAt; a.ldbat = ldbat;
-    a.RSQ = RSQ; a.stRSQ = stageRSQ; a.sRSQ = strideRSQ; a.ldrsq = ldrsq;
-    a.QN = QN; a.sQ = strideQ; a.ldq = ldq;
-    a.F = F; a.stF = stageF; a.sF = strideF; a.ldf = ldf;
-    a.LN = LN; a.sL = strideL; a.ldl = ldl;
-    a.info = info;
-    a.work = (double *)work;
-    a.batch = batch;
-    return to_status(mb::launch_riccati(a, waves, stream));
+    return riccati_call(nx, nu, N, BAt, ldbat, stageBAt, strideBAt, RSQ, ldrsq, stageRSQ,
+                        strideRSQ, QN, ldq, strideQ, F, ldf, stageF, strideF, LN, ldl, strideL,
+                        info, work, work_bytes, batch, stream, false);
+}
+
+int mb_riccati_strided_batched_noalloc(int nx, int nu, int N, const double *BAt, int ldbat,
+                                       int64_t stageBAt, int64_t strideBAt, const double *RSQ,
+                                       int ldrsq, int64_t stageRSQ, int64_t strideRSQ,
+                                       const double *QN, int ldq, int64_t strideQ, double *F,
+                                       int ldf, int64_t stageF, int64_t strideF, double *LN,
+                                       int ldl, int64_t strideL, int *info, int batch,
+                                       hipStream_t stream)
+{
+    return riccati_call(nx, nu, N, BAt, ldbat, stageBAt, strideBAt, RSQ, ldrsq, stageRSQ,
+                        strideRSQ, QN, ldq, strideQ, F, ldf, stageF, strideF, LN, ldl, strideL,
+                        info, nullptr, 0, batch, stream, true);
 }
 
 const char *mb_status_string(int status)
@@ -718,6 +754,8 @@ const char *mb_status_string(int status)
     if (status == MB_ERR_HIP) return "HIP runtime or launch failure";
     if (status == MB_ERR_UNSUPPORTED) return "unsupported argument combination";
     if (status == MB_ERR_INVALID_PROBLEM) return "a plan problem failed validation";
+    if (status == MB_ERR_SCRATCH)
+        return "the problem needs more device scratch than the allocation-free entry point holds";
     if (status < 0 && status > -64) return "illegal value of argument -status";
     return "unknown status";
 }

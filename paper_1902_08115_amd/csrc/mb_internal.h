@@ -258,6 +258,11 @@ hipError_t launch_syrk_ln(const SyrkArgs &a, hipStream_t s);
 int64_t riccati_slot_doubles(int nx, int nu);  // workspace of one wave
 hipError_t riccati_max_waves(int nx, int nu, int *waves);  // waves resident at once
 hipError_t launch_riccati(const RiccatiArgs &a, int waves, hipStream_t s);
+// Device scratch of the allocation-free Riccati entry point: the calling
+// device's address of a file-scope array of RIC_SCRATCH_BYTES (resolved once
+// per device; nothing is allocated).
+constexpr size_t RIC_SCRATCH_BYTES = size_t(64) << 20;
+hipError_t riccati_scratch(void **ptr, size_t *bytes);
 
 // Validated dgemm / dpotrf launches used by the C ABI and by plans (api.hip):
 // quick returns, size-class dispatch, launch.  Return an MB_ status.

@@ -31,6 +31,9 @@
 // and a slot is rewritten problem after problem while it is still cached.
 #include <limits.h>
 
+#include <atomic>
+#include <mutex>
+
 #include <type_traits>
 
 #include "potrf_wave.h"
@@ -410,6 +413,48 @@ hipError_t launch_riccati(const RiccatiArgs &a, int waves, hipStream_t s)
     else
         hipLaunchKernelGGL(riccati_kernel<0>, dim3(blocks), dim3(RIC_WPB * 64), 0, s, a, waves);
     return hipGetLastError();
+}
+
+// ---- device scratch of the allocation-free entry point -----------------------
+// mb_riccati_strided_batched_noalloc takes its workspace slots from this
+// file-scope array instead of a caller's buffer.  Each device holds its own
+// copy (RIC_SCRATCH_BYTES, from the first load of this library until the
+// process ends) at its own address.  In host code the name `scratch` stands
+// for a host-side shadow, not for device memory: host code must only pass
+// the address riccati_scratch() resolves.  Every call on one device shares
+// the array, so calls that overlap in time on one device race.  The kernel
+// writes every slot element before reading it within each problem, so the
+// array needs no clearing between calls.
+static __device__ __align__(256) double scratch[RIC_SCRATCH_BYTES / sizeof(double)];
+
+hipError_t riccati_scratch(void **ptr, size_t *bytes)
+{
+    constexpr int MAX_DEVICES = 64;
+    static std::atomic<void *> addr[MAX_DEVICES];
+    static std::mutex mu;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= MAX_DEVICES)
+        return hipErrorInvalidDevice;
+    void *p = addr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        // resolved once per device, with that device current
+        std::lock_guard<std::mutex> lock(mu);
+        p = addr[dev].load(std::memory_order_relaxed);
+        if (!p) {
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess)
+                return e;
+            if (!p)
+                return hipErrorInvalidSymbol;
+            addr[dev].store(p, std::memory_order_release);
+        }
+    }
+    *ptr = p;
+    *bytes = RIC_SCRATCH_BYTES;
+    return hipSuccess;
 }
 
 }  // namespace mb

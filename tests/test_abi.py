@@ -306,6 +306,37 @@ def test_riccati_argument_errors(L):
     assert L.riccati_workspace_size(300, 5, 1)[0] == L.MB_ERR_UNSUPPORTED
 
 
+def test_riccati_noalloc_argument_errors(L):
+    """The allocation-free Riccati entry point validates like the workspace
+    one (without work / work_bytes: batch is argument 23) before it touches
+    the device scratch; batch 0 and nx + nu > 304 return before it too."""
+    nx, nu, N, b = 8, 4, 3, 2
+    m = nx + nu
+    sf = m * m
+    ok = dict(nx=nx, nu=nu, N=N, BAt=P, ldbat=m, stBAt=m * nx, sBAt=N * m * nx, RSQ=P, ldrsq=m,
+              stRSQ=sf, sRSQ=N * sf, QN=P, ldq=nx, sQ=nx * nx, F=P, ldf=m, stF=sf, sF=N * sf,
+              LN=P, ldl=nx, sL=nx * nx, info=P, batch=b, stream=None)
+    order = list(ok)
+
+    def call(**kw):
+        a = dict(ok)
+        a.update(kw)
+        return L.riccati_strided_batched_noalloc(*[a[k] for k in order])
+
+    bad = [("nx", -1, -1), ("nu", -1, -2), ("N", -1, -3), ("ldbat", m - 1, -5), ("stBAt", -1, -6),
+           ("sBAt", -1, -7), ("ldrsq", m - 1, -9), ("stRSQ", -1, -10), ("sRSQ", -1, -11),
+           ("ldq", nx - 1, -13), ("sQ", -1, -14), ("ldf", m - 1, -16), ("stF", sf - 1, -17),
+           ("sF", N * sf - 1, -18), ("ldl", nx - 1, -20), ("sL", nx * nx - 1, -21),
+           ("batch", -1, -23), ("BAt", None, -4), ("RSQ", None, -8), ("QN", None, -12),
+           ("F", None, -15), ("LN", None, -19), ("info", None, -22)]
+    for key, val, want in bad:
+        assert call(**{key: val}) == want, (key, val)
+    assert call(batch=0) == 0
+    assert call(nx=300, nu=5, ldbat=305, ldrsq=305, ldq=300, ldf=305, ldl=300, stF=305 * 305,
+                sF=N * 305 * 305, sL=300 * 300) == L.MB_ERR_UNSUPPORTED
+    assert "scratch" in L.status_string(L.MB_ERR_SCRATCH)
+
+
 def test_trmm_syrk_argument_errors(L):
     """Illegal arguments of the batched dtrmm_rlnn and dsyrk_ln return their
     positions; quick returns succeed without a GPU."""
