@@ -26,8 +26,6 @@ __global__ __launch_bounds__(IPB * 64) __attribute__((amdgpu_waves_per_eu(2))) v
     // faster than the plain ones from 8 tiles (n = 128..240) and faster at
     // n = 256..304; below 8 tiles the plain loops keep more waves per SIMD
     constexpr bool PIPE = NT >= 8;
-    // one tile: the unrolled diagonal factorization costs no occupancy there
-    constexpr bool UNROLL = NT == 1;
     // panel rows per group: more rows share each load of the pivot columns'
     // tiles (fewer re-reads) at more registers -- 3 with the pipelined loops
     // (4 would spill there), 2 below 8 tiles
@@ -38,7 +36,7 @@ __global__ __launch_bounds__(IPB * 64) __attribute__((amdgpu_waves_per_eu(2))) v
     // tiles); the plain-loop orders keep none -- there the extra registers
     // cost a wave per SIMD
     constexpr int G1 = PIPE ? ((NT % 2 == 1 || NT < 12) ? 2 : 3) : 0;
-    const int info = potrf_wave<true, G, PIPE, UNROLL, G1, KC>(A, (size_t)p.lda, p.n, NT, smem[inst],
+    const int info = potrf_wave<true, G, PIPE, G1, KC>(A, (size_t)p.lda, p.n, NT, smem[inst],
                                                                 lane, pcache[inst]);
     if (lane == 0)
         p.info[b] = info;

@@ -40,17 +40,24 @@
 
 #include <limits.h>
 
+#include <utility>
+
 #include "mb_internal.h"
 
 namespace mb {
 
-// Per-wave LDS for broadcasting the column being eliminated in the diagonal
-// tile (double-buffered by column parity).
+// Per-wave LDS of the diagonal-tile factorization: the lower triangle of the
+// tile, packed by columns (element (a, b), a >= b, at tri_pos(a, b)), so that
+// every lane can read its whole symmetric row.
 struct PotrfSmem {
-    double col[2][16];   // column being eliminated (diagonal tile)
-    double xrow[2][16];  // row of L^{-1} being propagated (diagonal tile)
-    int fail;            // first failing global column, INT_MAX if none
+    double tile[136];
+    int fail;  // first failing global column, INT_MAX if none
 };
+
+__device__ __forceinline__ int tri_pos(int a, int b)
+{
+    return 16 * b - (b * (b - 1)) / 2 + (a - b);
+}
 
 // 1/sqrt(a) for a positive normal a: the hardware estimate refined by two
 // Newton-Raphson steps for f(y) = 1/y^2 - a, y <- y + y (1 - a y^2) / 2
@@ -66,94 +73,115 @@ __device__ __forceinline__ double rsqrt_nr(double a)
     return y;
 }
 
+// Lane C of every row of 16 lanes, broadcast to the whole row (one 64-bit DPP
+// move, row_newbcast).
+template <int C>
+__device__ __forceinline__ double row_bcast(double v)
+{
+    return __builtin_amdgcn_mov_dpp(v, 0x150 + C, 0xF, 0xF, true);
+}
+
+// Value of v in lane `src` (every lane may name a different source; the LDS
+// crossbar, no LDS memory).
+__device__ __forceinline__ double lane_read(double v, int src)
+{
+    const int2 w = __builtin_bit_cast(int2, v);
+    const int addr = src * 4;
+    int2 r;
+    r.x = __builtin_amdgcn_ds_bpermute(addr, w.x);
+    r.y = __builtin_amdgcn_ds_bpermute(addr, w.y);
+    return __builtin_bit_cast(double, r);
+}
+
+// Elimination step C of the diagonal-tile factorization, on tiles in
+// accumulator order (lane (g, i), register r: row i, column g + 4r).  T is
+// the whole symmetric trailing matrix; every finished row and column of it
+// is zero (up to rounding), so the step needs no masks:
+//   l_iC = T[i][C] / sqrt(T[C][C]);  T[i][q] -= (T[i][C] / T[C][C]) T[C][q]
+// for every i, q -- which also clears row and column C.  T[C][q] is register
+// r of lane (g, C), the same group and register: one DPP broadcast within the
+// row of 16; T[i][C] is register C/4 of lane (C%4, i): one crossbar read;
+// the pivot is T[C][C] of lane (g, C), broadcast likewise.  Column C of the factor goes to register C/4
+// of group C%4 of lo (zero above the diagonal).  With INV, X = L^{-1} (same
+// order) is updated alongside, X <= C_C^{-1} X for the column factor C_C of L:
+// row C is divided by l_CC and rows i > C lose l_iC / l_CC times the old row
+// C -- one fma with the DPP-broadcast old row C (multiplier 1 - 1/l_CC on row
+// C; rows i < C have multiplier T[i][C] / T[C][C] = 0).  A step past `cols`,
+// at a pivot that is not positive, or after such a pivot, is inactive: zero
+// multipliers and lo keeps its identity column.  The first failing column
+// goes to fc.  No branches: the state never needs merging.
+template <int C, bool INV>
+__device__ __forceinline__ void elim_step(d4 &t, d4 &lo, d4 &x, int lane, int cols, int &fc)
+{
+    constexpr int RC = C >> 2, GC = C & 3;
+    // an opaque copy of the lane index: the lane masks below are then formed
+    // where they are used (one compare each) instead of being hoisted out of
+    // the callers' loops, 48 of them held in scalar registers
+    asm volatile("" : "+v"(lane));
+    const int i = lane & 15, g = lane >> 4;
+    const double col = lane_read(t[RC], 16 * GC + i);  // T[i][C]
+    const double piv = row_bcast<C>(col);              // T[C][C]
+    const bool live = C < cols && fc == 16;
+    const bool act = live && piv > 0.0;
+    fc = (live && !act) ? C : fc;
+    // an inactive step takes rs = 1 exactly (so 1 - rs = 0)
+    const double rs = rsqrt_nr(act ? piv : 1.0);
+    const double l = col * rs;
+    const double lr = act ? l * rs : 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        t[r] = fma(-lr, row_bcast<C>(t[r]), t[r]);
+    if (g == GC && act)
+        lo[RC] = (i >= C) ? l : 0.0;
+    if (INV) {
+        const double ms = (i == C) ? 1.0 - rs : lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            x[r] = fma(-ms, row_bcast<C>(x[r]), x[r]);
+    }
+}
+
+template <bool INV, int... C>
+__device__ __forceinline__ void elim_steps(d4 &t, d4 &lo, d4 &x, int lane, int cols, int &fc,
+                                           std::integer_sequence<int, C...>)
+{
+    (elim_step<C, INV>(t, lo, x, lane, cols, fc), ...);
+}
+
 // Factor one 16x16 diagonal tile held in accumulator order -- lane (g, i),
-// register r holds T[i][g + 4r] -- by one whole wave (inner_edge_dpotrf).
-// Column c is eliminated in step c: its entries on and below the diagonal are
-// published through LDS (zeros above it), every lane forms
-// l_ic = T[i][c] / sqrt(t_cc) for its row and updates its four entries
-// T[i][q] -= l_ic * l_qc.  The published zeros make the update a no-op for
-// the finished columns q < c, and the entries above the diagonal that it
-// touches are cleared at the end, so no lane needs a mask.  With INV,
-// X = L^{-1} is accumulated alongside as the product of inverted column
-// factors (X <= C_c^{-1} X, C_c the identity except for column c of L): row c
-// is scaled by 1/l_cc and rows i > c lose l_ic times it; row c of X is
-// published with column c+1 of T, so each step costs a single LDS round trip.
-// Only the first `cols` columns are eliminated: the rest of the tile is the
-// identity padding of an order that is not a multiple of 16.  A failing pivot
-// at column c is recorded in S.fail; columns c..15 then become the identity
-// so that L stays invertible.  On exit t holds L (upper part zero) and, with
-// INV, x holds L^{-1}, both in accumulator order -- exactly the left-operand
-// order the panel MFMA needs.  UNROLL unrolls the 16 steps (about half the
-// instructions per step, since register indices become constants, but more
-// registers): for kernels whose occupancy does not suffer from it.
-template <bool INV, bool UNROLL = false, class Smem>
+// register r holds T[i][g + 4r], lower triangle valid -- by one whole wave
+// (inner_edge_dpotrf).  The tile is made symmetric through LDS (entries right
+// of the diagonal read back from the lower triangle), then the columns are
+// eliminated in order (elim_step).  Only the first `cols` columns are
+// eliminated: the rest of the tile is the identity padding of an order that
+// is not a multiple of 16.  A failing pivot at column c is recorded in S.fail
+// (as 16 J + c); columns c..15 of L are then the identity, so that L stays
+// invertible.  On exit t holds L (upper part zero) and, with INV, x holds
+// L^{-1}, both in accumulator order -- exactly the left-operand order the
+// panel MFMA needs.
+template <bool INV, class Smem>
 __device__ __forceinline__ void factor_diag_tile(d4 &t, d4 &x, Smem &S, int J, int lane,
                                                  int cols = 16)
 {
     const int i = lane & 15, g = lane >> 4;
-    if (INV) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            x[r] = (i == g + 4 * r) ? 1.0 : 0.0;
-    }
-    bool failed = false;
-    double lprev = 0.0;  // l_{i,c-1} of the previous step for rows i > c-1, else 0
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        if (c >= cols) {
-            if (UNROLL)
-                continue;  // the loop stays fully unrolled: c is a constant in every step
-            break;         // a rolled loop: fewer registers, more instructions per step
-        }
-        const int buf = c & 1;
-        // publish column c of T (on and below the diagonal) and, from step 1
-        // on, the scaled row c-1 of X
-        if (g == (c & 3))
-            S.col[buf][i] = (i >= c) ? t[c >> 2] : 0.0;
-        if (INV && c > 0 && i == c - 1) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                S.xrow[buf][g + 4 * r] = x[r];
-        }
-        wave_lds_sync();
-        // X update of step c-1: rows i > c-1 lose l_{i,c-1} * (scaled row c-1)
-        if (INV && c > 0) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                x[r] = fma(-lprev, S.xrow[buf][g + 4 * r], x[r]);
-        }
-        const double piv = S.col[buf][c];
-        if (!failed && !(piv > 0.0)) {
-            failed = true;  // uniform: every lane read the same pivot
-            if (lane == 0)
-                S.fail = 16 * J + c;
-        }
-        double rinv = 1.0, li;
-        if (!failed) {
-            rinv = rsqrt_nr(piv);
-            li = S.col[buf][i] * rinv;  // l_cc = t_cc / sqrt(t_cc) on the diagonal
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                t[r] = fma(-li, S.col[buf][g + 4 * r] * rinv, t[r]);
-        } else {
-            li = (i == c) ? 1.0 : 0.0;
-        }
-        if (g == (c & 3))
-            t[c >> 2] = li;
-        if (INV) {
-            if (i == c) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    x[r] *= rinv;
-            }
-            lprev = (i > c) ? li : 0.0;
-        }
-    }
-    // zero the strict upper part of L
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-        if (g + 4 * r > i)
-            t[r] = 0.0;
+        if (i >= g + 4 * r)
+            S.tile[tri_pos(i, g + 4 * r)] = t[r];
+    wave_lds_sync();
+    d4 lo;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int q = g + 4 * r;
+        t[r] = S.tile[q <= i ? tri_pos(i, q) : tri_pos(q, i)];
+        lo[r] = (q == i) ? 1.0 : 0.0;
+        x[r] = lo[r];
+    }
+    int fc = 16;
+    elim_steps<INV>(t, lo, x, lane, cols, fc, std::make_integer_sequence<int, 16>{});
+    if (fc < 16 && lane == 0)
+        S.fail = 16 * J + fc;
+    t = lo;
 }
 
 // Load tile (I, K) in accumulator order.  diag: the tile of A on the
@@ -248,7 +276,7 @@ __device__ __forceinline__ d4 lds_get_tile(const double *pc, int t, int lane)
 // 2 KC tiles: the diagonal block's loop keeps the
 // pivot tiles L(J,K), L(J1,K) of its first KC steps there, and every later
 // panel group takes those steps from LDS instead of reading them again.
-template <bool PAIR, int G = 2, bool PIPE = true, bool UNROLL = false, int G1 = 0, int KC = 0>
+template <bool PAIR, int G = 2, bool PIPE = true, int G1 = 0, int KC = 0>
 __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT, PotrfSmem &S,
                                           int lane, double *pc = nullptr)
 {
@@ -363,7 +391,7 @@ __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT
             }
         }
         d4 w0, w1 = d4{0.0, 0.0, 0.0, 0.0};
-        factor_diag_tile<true, UNROLL>(t00, w0, S, J, lane, n - 16 * J);
+        factor_diag_tile<true>(t00, w0, S, J, lane, n - 16 * J);
         wave_lds_sync();
         int fail_col = S.fail;
         store_diag(A, lda, n, J, t00, fail_col, lr, lg);
@@ -373,7 +401,7 @@ __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT
             store_tile(A, lda, n, J1, J, l10, fail_col, lr, lg);
             if (fail_col == INT_MAX) {
                 t11 = update_nt(t11, l10, l10);
-                factor_diag_tile<true, UNROLL>(t11, w1, S, J1, lane, n - 16 * J1);
+                factor_diag_tile<true>(t11, w1, S, J1, lane, n - 16 * J1);
                 wave_lds_sync();
                 fail_col = S.fail;
                 store_diag(A, lda, n, J1, t11, fail_col, lr, lg);
