@@ -274,5 +274,7 @@ const char *potrf_kernel_name(int n);
 
 // Largest order handled by the register-resident Cholesky kernel.
 constexpr int POTRF_MAX_N = 19 * 16;
+// Largest order factored with whole rows in lanes (four instances per wave).
+constexpr int POTRF_ROWS_MAX_N = 32;
 
 }  // namespace mb

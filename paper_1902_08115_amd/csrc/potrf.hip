@@ -5,6 +5,12 @@
 // that every loop bound is a constant.
 #include "potrf_wave.h"
 
+#include <utility>
+
+#ifndef POTRF_ROWS_IPW
+#define POTRF_ROWS_IPW 4
+#endif
+
 namespace mb {
 
 template <int NT, int IPB>
@@ -42,6 +48,130 @@ __global__ __launch_bounds__(IPB * 64) __attribute__((amdgpu_waves_per_eu(2))) v
         p.info[b] = info;
 }
 
+// ---- orders up to 32: four instances per wave, whole rows in lanes ----------
+// For small orders what costs is the chain of N elimination steps, not
+// arithmetic.  Lane (g, i) of a wave holds rows i and, from order 17, i + 16
+// of instance 4w + g whole (entries right of the diagonal read from the lower
+// triangle, by symmetry), so the pivot row of step C -- row C, in lane C % 16
+// of the lane's own group of 16 -- reaches the group by one DPP broadcast per
+// entry, each broadcast serves both rows of a lane, and each instruction
+// serves four instances.  The order N is a template parameter: exactly N
+// steps, with every register index a constant.  No matrix cores, no LDS.
+
+// Elimination step C on rows i + 16 s (s < S) held whole in R[s][0..N):
+// rows below C get l_kC = R[C] / sqrt(piv) and lose (R[C] / piv) times the
+// pivot row right of C; row C itself becomes [.., sqrt(piv), 0 ..] (the
+// update clears the entries right of its diagonal); rows above C have
+// R[C] = 0 and do not change.  A step at a pivot that is not positive, or
+// after one, changes nothing (zero multiplier; fc keeps the first failing
+// column).  Branch-free: the four instances of a wave fail independently.
+template <int N, int S, int C>
+__device__ __forceinline__ void rows_step(double (&R)[S][N], int &fc)
+{
+    constexpr int CL = C % 16, CS = C / 16;
+    const double piv = row_bcast<CL>(R[CS][C]);
+    const bool live = fc == N;
+    const bool act = live && piv > 0.0;
+    fc = (live && !act) ? C : fc;
+    const double rs = rsqrt_nr(act ? piv : 1.0);
+    double l[S], lr[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        l[k] = R[k][C] * rs;
+        lr[k] = act ? l[k] * rs : 0.0;
+    }
+    // all broadcasts first, each into its own register: they are independent,
+    // and a shared temporary would make every broadcast wait for the fma
+    // before it
+    double pr[N];
+#pragma unroll
+    for (int q = C + 1; q < N; ++q)
+        pr[q] = row_bcast<CL>(R[CS][q]);
+#pragma unroll
+    for (int q = C + 1; q < N; ++q) {
+#pragma unroll
+        for (int k = 0; k < S; ++k)
+            R[k][q] = fma(-lr[k], pr[q], R[k][q]);
+    }
+#pragma unroll
+    for (int k = 0; k < S; ++k)
+        R[k][C] = act ? l[k] : R[k][C];
+}
+
+template <int N, int S, int... C>
+__device__ __forceinline__ void rows_steps(double (&R)[S][N], int &fc,
+                                           std::integer_sequence<int, C...>)
+{
+    (rows_step<N, S, C>(R, fc), ...);
+}
+
+template <int N, int IPW>
+__global__ __launch_bounds__(256) void potrf_rows_kernel(PotrfArgs p)
+{
+    constexpr int S = (N + 15) / 16;  // rows per lane
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = lane & 15, g = lane >> 4;
+    // IPW instances per wave: groups g >= IPW repeat group g % IPW and store
+    // nothing (fewer instances per wave: more waves to hide memory latency)
+    const int64_t b = ((int64_t)blockIdx.x * 4 + wave) * IPW + (g % IPW);
+    // lanes of a missing instance, and rows past N, compute on zero rows
+    // (their results are never stored), so every lane takes part in the
+    // broadcasts
+    const bool inst = b < p.batch;
+    const MB_GLOBAL double *A =
+        global_ptr((const double *)inst_ptr(p.A, p.Aarr, p.sA, inst ? b : 0));
+    const size_t lda = (size_t)p.lda;
+    // every load is unconditional, from an address inside instance b (or
+    // instance 0 for a missing one; rows past N read row N-1), and only the
+    // value is selected: a load under a branch makes the compiler wait for it
+    // before the next one is issued
+    double R[S][N];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const int ii = i + 16 * k;
+        const bool row = inst && ii < N;
+        const size_t ic = (size_t)min(ii, N - 1);
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const double v = A[(size_t)q <= ic ? ic + (size_t)q * lda : (size_t)q + ic * lda];
+            R[k][q] = row ? v : 0.0;
+        }
+    }
+    int fc = N;
+    rows_steps<N, S>(R, fc, std::make_integer_sequence<int, N>{});
+    if (inst && g < IPW) {
+        MB_GLOBAL double *Aw = global_ptr(inst_ptr(p.A, p.Aarr, p.sA, b));
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            const int ii = i + 16 * k;
+#pragma unroll
+            for (int q = 0; q < N; ++q)
+                if (ii < N && q <= ii && q < fc)
+                    Aw[(size_t)ii + (size_t)q * lda] = R[k][q];
+        }
+        if (i == 0)
+            p.info[b] = fc == N ? 0 : fc + 1;
+    }
+}
+
+template <int N>
+static hipError_t launch_potrf_rows(const PotrfArgs &a, hipStream_t s)
+{
+    constexpr int IPW = POTRF_ROWS_IPW;
+    const int64_t blocks = ((int64_t)a.batch + 4 * IPW - 1) / (4 * IPW);  // four waves per workgroup
+    hipLaunchKernelGGL((potrf_rows_kernel<N, IPW>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int... N>
+static hipError_t launch_potrf_rows_n(int n, const PotrfArgs &a, hipStream_t s,
+                                      std::integer_sequence<int, N...>)
+{
+    hipError_t e = hipErrorInvalidValue;
+    (void)((n == N + 1 ? (e = launch_potrf_rows<N + 1>(a, s), true) : false) || ...);
+    return e;
+}
+
 __global__ void fill_info_kernel(int *info, int batch)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -60,10 +190,10 @@ static hipError_t launch_potrf_t(const PotrfArgs &a, hipStream_t s)
 
 hipError_t launch_potrf_lower(const PotrfArgs &a, hipStream_t s)
 {
+    if (a.n <= POTRF_ROWS_MAX_N)
+        return launch_potrf_rows_n(a.n, a, s, std::make_integer_sequence<int, POTRF_ROWS_MAX_N>{});
     const int nt = (a.n + 15) / 16;
     switch (nt) {
-    case 1: return launch_potrf_t<1, 4>(a, s);
-    case 2: return launch_potrf_t<2, 4>(a, s);
     case 3: return launch_potrf_t<3, 4>(a, s);
     case 4: return launch_potrf_t<4, 4>(a, s);
     case 5: return launch_potrf_t<5, 4>(a, s);
@@ -88,7 +218,7 @@ hipError_t launch_potrf_lower(const PotrfArgs &a, hipStream_t s)
 const char *potrf_kernel_name(int n)
 {
     static const char *names[20] = {
-        "potrf_fill_info", "potrf_nt1", "potrf_nt2", "potrf_nt3", "potrf_nt4", "potrf_nt5",
+        "potrf_fill_info", "potrf_rows", "potrf_rows2", "potrf_nt3", "potrf_nt4", "potrf_nt5",
         "potrf_nt6", "potrf_nt7", "potrf_nt8", "potrf_nt9", "potrf_nt10", "potrf_nt11",
         "potrf_nt12", "potrf_nt13", "potrf_nt14", "potrf_nt15", "potrf_nt16", "potrf_nt17",
         "potrf_nt18", "potrf_nt19"};

@@ -128,16 +128,28 @@ __device__ __forceinline__ void elim_step(d4 &t, d4 &lo, d4 &x, int lane, int co
     const double rs = rsqrt_nr(act ? piv : 1.0);
     const double l = col * rs;
     const double lr = act ? l * rs : 0.0;
+    // the broadcasts first, each into its own register: they are
+    // independent, and a shared temporary would make every broadcast wait
+    // for the fma before it
+    d4 tb, xb;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-        t[r] = fma(-lr, row_bcast<C>(t[r]), t[r]);
+        tb[r] = row_bcast<C>(t[r]);
+    if (INV) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            xb[r] = row_bcast<C>(x[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        t[r] = fma(-lr, tb[r], t[r]);
     if (g == GC && act)
         lo[RC] = (i >= C) ? l : 0.0;
     if (INV) {
         const double ms = (i == C) ? 1.0 - rs : lr;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            x[r] = fma(-ms, row_bcast<C>(x[r]), x[r]);
+            x[r] = fma(-ms, xb[r], x[r]);
     }
 }
 

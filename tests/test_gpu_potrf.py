@@ -54,12 +54,13 @@ def test_sweep_sizes_with_failing_instance(si, n):
         assert d <= POTRF_TOL, d
 
 
-@pytest.mark.parametrize("n", [1, 2, 5, 15, 16, 17, 31, 33, 47, 64, 65, 90, 100, 128, 129, 150, 176,
-                               185, 200, 224, 237, 256, 272, 288, 300, 304])
+@pytest.mark.parametrize("n", list(range(1, 33)) + [33, 47, 64, 65, 90, 100, 128, 129, 150, 176,
+                                                  185, 200, 224, 237, 256, 272, 288, 300, 304])
 def test_exact_integer_factor(n):
     """A = L0 L0^T with integer L0 (diagonal in {1,2,4}): the factor is L0
     exactly for any evaluation order, so the GPU result must match bit for bit.
-    The orders reach every tile count 1..19 (each its own kernel instance)."""
+    The orders reach every tile count 1..19 and every order up to 32 (each its
+    own kernel instance)."""
     g = inputs.rng(8000 + n)
     batch = 3
     A = np.full((batch, n, n + 1), np.nan)
@@ -103,6 +104,39 @@ def test_info_in_pipelined_orders(n):
         d = np.linalg.norm((Lg - Lr)[low]) / np.linalg.norm(Lr[low])
         assert d <= POTRF_TOL, (j, d)
         assert np.isnan(Ag[b].T[:n, :n][np.triu_indices(n, 1)]).all(), "upper touched"
+
+
+@pytest.mark.parametrize("n", [9, 16, 24, 32])
+def test_info_rows_orders_every_column(n):
+    """Orders factored with whole rows in lanes, four instances per wave: a_jj
+    = -1 in instance j for every column j (plus one SPD instance; n + 1
+    instances, so the last wave is ragged), strictly upper triangle NaN and
+    padded ld.  info is j+1 in instance j (each of a wave's four instances
+    fails independently), the columns before j match the oracle's partial
+    factor, the upper triangle and the padding are never written."""
+    import oracle
+    g = inputs.rng(8170 + n)
+    batch = n + 1
+    ld = n + 3
+    A = inputs.spd_batch(g, batch, n, ld=ld, upper_value=np.nan)
+    for j in range(n):
+        A[j, j, j] = -1.0
+    say(f"dpotrf info rows n={n}")
+    Ag, info = _run(n, A, batch)
+    assert list(info) == list(range(1, n + 1)) + [0], info
+    for b in range(batch):
+        Lr = np.ascontiguousarray(A[b:b + 1]).ravel().copy()
+        want = b + 1 if b < n else 0
+        assert oracle.dpotrf_l_raw(n, Lr, ld) == want
+        j = b if b < n else n
+        Lr = Lr.reshape(A[b:b + 1].shape)[0]
+        if j > 0:
+            low = np.tril(np.ones((n, j), dtype=bool))
+            Lrj, Lgj = Lr.T[:n, :j], Ag[b].T[:n, :j]
+            d = np.linalg.norm((Lgj - Lrj)[low]) / np.linalg.norm(Lrj[low])
+            assert d <= POTRF_TOL, (b, j, d)
+        assert np.isnan(Ag[b].T[:n, :n][np.triu_indices(n, 1)]).all(), "upper touched"
+        assert np.array_equal(Ag[b][:, n:], A[b][:, n:], equal_nan=True), "padding touched"
 
 
 def test_info_closed_form_every_column():
