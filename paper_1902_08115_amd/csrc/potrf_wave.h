@@ -106,14 +106,21 @@ __device__ __forceinline__ double lane_read(double v, int src)
 // order) is updated alongside, X <= C_C^{-1} X for the column factor C_C of L:
 // row C is divided by l_CC and rows i > C lose l_iC / l_CC times the old row
 // C -- one fma with the DPP-broadcast old row C (multiplier 1 - 1/l_CC on row
-// C; rows i < C have multiplier T[i][C] / T[C][C] = 0).  A step past `cols`,
-// at a pivot that is not positive, or after such a pivot, is inactive: zero
-// multipliers and lo keeps its identity column.  The first failing column
-// goes to fc.  No branches: the state never needs merging.
-template <int C, bool INV>
+// C; rows i < C have multiplier T[i][C] / T[C][C] = 0).  A step past `cols`
+// is skipped; a step at a pivot that is not positive, or after one, is
+// inactive: zero multipliers, and lo keeps its identity column.  The first
+// failing column goes to fc.  No data-dependent branches: the state never
+// needs merging.
+template <int C, bool INV, bool SKIP>
 __device__ __forceinline__ void elim_step(d4 &t, d4 &lo, d4 &x, int lane, int cols, int &fc)
 {
     constexpr int RC = C >> 2, GC = C & 3;
+    // with SKIP, columns past the order (identity padding) are skipped by a
+    // scalar branch (cols is uniform over the wave); without it they run as
+    // inactive steps, which keeps the registers of callers whose tiles are
+    // mostly full from being spent on merging the branches
+    if (SKIP && C >= cols)
+        return;
     // an opaque copy of the lane index: the lane masks below are then formed
     // where they are used (one compare each) instead of being hoisted out of
     // the callers' loops, 48 of them held in scalar registers
@@ -121,7 +128,7 @@ __device__ __forceinline__ void elim_step(d4 &t, d4 &lo, d4 &x, int lane, int co
     const int i = lane & 15, g = lane >> 4;
     const double col = lane_read(t[RC], 16 * GC + i);  // T[i][C]
     const double piv = row_bcast<C>(col);              // T[C][C]
-    const bool live = C < cols && fc == 16;
+    const bool live = (SKIP || C < cols) && fc == 16;
     const bool act = live && piv > 0.0;
     fc = (live && !act) ? C : fc;
     // an inactive step takes rs = 1 exactly (so 1 - rs = 0)
@@ -153,11 +160,11 @@ __device__ __forceinline__ void elim_step(d4 &t, d4 &lo, d4 &x, int lane, int co
     }
 }
 
-template <bool INV, int... C>
+template <bool INV, bool SKIP, int... C>
 __device__ __forceinline__ void elim_steps(d4 &t, d4 &lo, d4 &x, int lane, int cols, int &fc,
                                            std::integer_sequence<int, C...>)
 {
-    (elim_step<C, INV>(t, lo, x, lane, cols, fc), ...);
+    (elim_step<C, INV, SKIP>(t, lo, x, lane, cols, fc), ...);
 }
 
 // Factor one 16x16 diagonal tile held in accumulator order -- lane (g, i),
@@ -166,12 +173,13 @@ __device__ __forceinline__ void elim_steps(d4 &t, d4 &lo, d4 &x, int lane, int c
 // of the diagonal read back from the lower triangle), then the columns are
 // eliminated in order (elim_step).  Only the first `cols` columns are
 // eliminated: the rest of the tile is the identity padding of an order that
-// is not a multiple of 16.  A failing pivot at column c is recorded in S.fail
-// (as 16 J + c); columns c..15 of L are then the identity, so that L stays
-// invertible.  On exit t holds L (upper part zero) and, with INV, x holds
+// is not a multiple of 16 (SKIP: callers whose tiles are mostly partial skip
+// the remaining steps by a scalar branch).  A failing pivot at column c is
+// recorded in S.fail (as 16 J + c); columns c..15 of L are then the identity,
+// so that L stays invertible.  On exit t holds L (upper part zero) and, with INV, x holds
 // L^{-1}, both in accumulator order -- exactly the left-operand order the
 // panel MFMA needs.
-template <bool INV, class Smem>
+template <bool INV, bool SKIP = false, class Smem>
 __device__ __forceinline__ void factor_diag_tile(d4 &t, d4 &x, Smem &S, int J, int lane,
                                                  int cols = 16)
 {
@@ -190,7 +198,7 @@ __device__ __forceinline__ void factor_diag_tile(d4 &t, d4 &x, Smem &S, int J, i
         x[r] = lo[r];
     }
     int fc = 16;
-    elim_steps<INV>(t, lo, x, lane, cols, fc, std::make_integer_sequence<int, 16>{});
+    elim_steps<INV, SKIP>(t, lo, x, lane, cols, fc, std::make_integer_sequence<int, 16>{});
     if (fc < 16 && lane == 0)
         S.fail = 16 * J + fc;
     t = lo;

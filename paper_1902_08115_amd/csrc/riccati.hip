@@ -347,7 +347,7 @@ __global__ __launch_bounds__(RIC_WPB * 64) void riccati_small_kernel(RiccatiArgs
             S.potrf.fail = INT_MAX;
         wave_lds_sync();
         d4 w;
-        factor_diag_tile<false>(f, w, S.potrf, 0, lane, n == N ? nx : m);
+        factor_diag_tile<false, true>(f, w, S.potrf, 0, lane, n == N ? nx : m);
         wave_lds_sync();
         const int fail = S.potrf.fail;
         const bool term = n == N;
