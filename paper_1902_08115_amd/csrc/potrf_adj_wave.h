@@ -22,14 +22,14 @@
 // by swapping the element coordinates.
 #pragma once
 
-#include "mb_internal.h"
+#include <utility>
+
+#include "potrf_wave.h"
 
 namespace mb {
 
 struct AdjSmem {
-    double col[2][16];   // column being eliminated (inversion), double-buffered
-    double xrow[2][16];  // row of the inverse being propagated
-    double t[16][17];    // tile transpose staging
+    double t[16][17];  // tile transpose staging
 };
 
 // The 16 x 16 block M with M[i][c] = X(R0 + i, C0 + c), or X(C0 + c, R0 + i)
@@ -79,41 +79,49 @@ __device__ __forceinline__ d4 adj_xyT(d4 acc, const d4 &x, const d4 &y, double s
     return acc;
 }
 
+// Step C of the inverse of a lower-triangular tile t (accumulator order,
+// nonzero diagonal): X <= C_C^{-1} X, where C_C is the identity with column C
+// replaced by column C of t -- row C of X is divided by t_CC and the rows
+// below lose t_iC / t_CC times it (rows above have t_iC = 0).  Both are one
+// fma with row C of X, which sits in the same register of lane C of each
+// group of 16 (a DPP broadcast); t_iC comes through the crossbar, t_CC from
+// lane C; the reciprocal is the hardware estimate refined by Newton-Raphson.
+template <int C>
+__device__ __forceinline__ void inv_step(const d4 &t, d4 &x, int lane)
+{
+    constexpr int RC = C >> 2, GC = C & 3;
+    // opaque lane index: the lane mask is formed here, not hoisted
+    asm volatile("" : "+v"(lane));
+    const int i = lane & 15;
+    const double lic = lane_read(t[RC], 16 * GC + i);  // t[i][C]
+    const double rinv = rcp_nr(row_bcast<C>(lic));    // 1 / t[C][C]
+    const double ms = (i == C) ? 1.0 - rinv : lic * rinv;
+    d4 xb;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        xb[r] = row_bcast<C>(x[r]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        x[r] = fma(-ms, xb[r], x[r]);
+}
+
+template <int... C>
+__device__ __forceinline__ void inv_steps(const d4 &t, d4 &x, int lane,
+                                          std::integer_sequence<int, C...>)
+{
+    (inv_step<C>(t, x, lane), ...);
+}
+
 // Inverse of a lower-triangular tile t (accumulator order, nonzero
-// diagonal): X = C_15^{-1} ... C_0^{-1}, where C_c is the identity with
-// column c replaced by column c of t; step c scales row c of X by 1 / t_cc
-// and subtracts t_ic times it from the rows below.  Column c of t and row c
-// of X are broadcast through LDS, one round trip per step.
-__device__ __forceinline__ d4 adj_inv_lower(const d4 &t, AdjSmem &S, int lane)
+// diagonal): X = C_15^{-1} ... C_0^{-1} (inv_step), no LDS.
+__device__ __forceinline__ d4 adj_inv_lower(const d4 &t, int lane)
 {
     const int i = lane & 15, g = lane >> 4;
     d4 x;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
         x[r] = (i == g + 4 * r) ? 1.0 : 0.0;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        const int buf = c & 1;
-        if (g == (c & 3))
-            S.col[buf][i] = t[c >> 2];
-        if (i == c) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                S.xrow[buf][g + 4 * r] = x[r];
-        }
-        wave_lds_sync();
-        const double rinv = 1.0 / S.col[buf][c];
-        const double lic = S.col[buf][i];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const double xc = S.xrow[buf][g + 4 * r] * rinv;
-            if (i == c)
-                x[r] = xc;
-            else if (i > c)
-                x[r] = fma(-lic, xc, x[r]);
-        }
-    }
-    wave_lds_sync();
+    inv_steps(t, x, lane, std::make_integer_sequence<int, 16>{});
     return x;
 }
 
@@ -131,6 +139,18 @@ __device__ __forceinline__ d4 adj_transpose(const d4 &x, AdjSmem &S, int lane)
         y[r] = S.t[g + 4 * r][i];
     wave_lds_sync();
     return y;
+}
+
+// adj_ld with trans: the mirrored block loaded in its own order (consecutive
+// lanes read consecutive rows of a column -- one cache line per 16 lanes)
+// and transposed through LDS.  Reading the transposed elements directly puts
+// 16 cache lines under every load instruction, which saturated the address
+// units.
+__device__ __forceinline__ d4 adj_ldt(const MB_GLOBAL double *X, size_t ld, int n, int R0, int C0,
+                                      bool lower, bool ident, AdjSmem &S, int lane)
+{
+    return adj_transpose(adj_ld(X, ld, n, C0, R0, false, lower, ident, lane & 15, lane >> 4), S,
+                         lane);
 }
 
 // Make this wave's global stores visible to its own later loads.
@@ -154,8 +174,8 @@ __device__ __forceinline__ void potrf_adj_wave(const double *Lp, size_t ldl, con
         for (int I = J; I < NT; ++I) {
             d4 acc = zero;
             for (int K = I; K < NT; ++K) {
-                const d4 lt = adj_ld(L, ldl, n, 16 * I, 16 * K, true, K == I, false, lr, lg);
-                const d4 bt = adj_ld(Lb, ldlb, n, 16 * J, 16 * K, true, K == J, false, lr, lg);
+                const d4 lt = adj_ldt(L, ldl, n, 16 * I, 16 * K, K == I, false, S, lane);
+                const d4 bt = adj_ldt(Lb, ldlb, n, 16 * J, 16 * K, K == J, false, S, lane);
                 acc = adj_xyT(acc, lt, bt, 1.0);
             }
             if (I == J) {
@@ -173,12 +193,12 @@ __device__ __forceinline__ void potrf_adj_wave(const double *Lp, size_t ldl, con
     // Z L = P, Z lower: Z(I,J) = (P(I,J) - sum_{J<K<=I} Z(I,K) L(K,J)) L_JJ^{-1}
     for (int J = NT - 1; J >= 0; --J) {
         const d4 ljj = adj_ld(L, ldl, n, 16 * J, 16 * J, false, true, true, lr, lg);
-        const d4 winv_t = adj_transpose(adj_inv_lower(ljj, S, lane), S, lane);  // L_JJ^{-T}
+        const d4 winv_t = adj_transpose(adj_inv_lower(ljj, lane), S, lane);  // L_JJ^{-T}
         for (int I = J; I < NT; ++I) {
             d4 acc = adj_ld(Ab, lda, n, 16 * I, 16 * J, false, false, false, lr, lg);
             for (int K = J + 1; K <= I; ++K) {
                 const d4 z = adj_ld(Ab, lda, n, 16 * I, 16 * K, false, false, false, lr, lg);
-                const d4 lt = adj_ld(L, ldl, n, 16 * J, 16 * K, true, false, false, lr, lg);
+                const d4 lt = adj_ldt(L, ldl, n, 16 * J, 16 * K, false, false, S, lane);
                 acc = adj_xyT(acc, z, lt, -1.0);  // - Z(I,K) L(K,J)
             }
             adj_st(Ab, lda, n, 16 * I, 16 * J, false, adj_xyT(zero, acc, winv_t, 1.0), lr, lg);
@@ -189,13 +209,12 @@ __device__ __forceinline__ void potrf_adj_wave(const double *Lp, size_t ldl, con
     // W L = Z^T: W(I,J) = (Z(J,I)^T - sum_{K>J} W(I,K) L(K,J)) L_JJ^{-1}
     for (int J = NT - 1; J >= 0; --J) {
         const d4 ljj = adj_ld(L, ldl, n, 16 * J, 16 * J, false, true, true, lr, lg);
-        const d4 winv_t = adj_transpose(adj_inv_lower(ljj, S, lane), S, lane);
+        const d4 winv_t = adj_transpose(adj_inv_lower(ljj, lane), S, lane);
         for (int I = 0; I < NT; ++I) {
-            d4 acc = I <= J ? adj_ld(Ab, lda, n, 16 * I, 16 * J, true, I == J, false, lr, lg)
-                            : zero;
+            d4 acc = I <= J ? adj_ldt(Ab, lda, n, 16 * I, 16 * J, I == J, false, S, lane) : zero;
             for (int K = J + 1; K < NT; ++K) {
                 const d4 w = adj_ld(Ab, lda, n, 16 * I, 16 * K, false, false, false, lr, lg);
-                const d4 lt = adj_ld(L, ldl, n, 16 * J, 16 * K, true, false, false, lr, lg);
+                const d4 lt = adj_ldt(L, ldl, n, 16 * J, 16 * K, false, false, S, lane);
                 acc = adj_xyT(acc, w, lt, -1.0);
             }
             adj_st(Ab, lda, n, 16 * I, 16 * J, false, adj_xyT(zero, acc, winv_t, 1.0), lr, lg);
@@ -207,14 +226,14 @@ __device__ __forceinline__ void potrf_adj_wave(const double *Lp, size_t ldl, con
     for (int J = 0; J < NT; ++J) {
         for (int I = J; I < NT; ++I) {
             const d4 a = adj_ld(Ab, lda, n, 16 * I, 16 * J, false, false, false, lr, lg);
-            const d4 b = adj_ld(Ab, lda, n, 16 * I, 16 * J, true, false, false, lr, lg);
+            const d4 b = adj_ldt(Ab, lda, n, 16 * I, 16 * J, false, false, S, lane);
             d4 s;
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 s[r] = 0.5 * (a[r] + b[r]);
             adj_st(Ab, lda, n, 16 * I, 16 * J, false, s, lr, lg);
-            if (I != J)
-                adj_st(Ab, lda, n, 16 * I, 16 * J, true, s, lr, lg);
+            if (I != J)  // the mirrored block, stored in its own order
+                adj_st(Ab, lda, n, 16 * J, 16 * I, false, adj_transpose(s, S, lane), lr, lg);
         }
     }
 }

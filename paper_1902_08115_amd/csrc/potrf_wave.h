@@ -73,6 +73,17 @@ __device__ __forceinline__ double rsqrt_nr(double a)
     return y;
 }
 
+// 1/a for a normal a: the hardware estimate refined by two Newton-Raphson
+// steps y <- y + y (1 - a y).
+__device__ __forceinline__ double rcp_nr(double a)
+{
+    double y = __builtin_amdgcn_rcp(a);
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        y = fma(y, fma(-a, y, 1.0), y);
+    return y;
+}
+
 // Lane C of every row of 16 lanes, broadcast to the whole row (one 64-bit DPP
 // move, row_newbcast).
 template <int C>
