@@ -514,7 +514,7 @@ def uneven_batch(torch, _lib, inputs, reps, modes=("fused_graph", "fused", "grou
                      "gflops": round(flops / best / 1e6, 1)}
         log(f"uneven batch {mode}: {best:.3f} ms ({flops / best / 1e6:.0f} GFLOP/s)")
     plan.close()
-    fb = res["fused_graph"]["best_ms"]
+    fb = res["fused_graph" if "fused_graph" in res else modes[0]]["best_ms"]
     grouped = {k: round(res[k]["best_ms"] / fb, 1) for k in ("grouped", "grouped_graph")
                if k in res}
     return {
@@ -784,10 +784,11 @@ def riccati_workload(torch, _lib, inputs, reps, composed=True):
 
 
 def compact_line(head, args, restore_bytes, peak_frac, roofline, cpu, per_size, ceil, parity,
-                 single, nxt):
-    """The one stdout line: the headline, the dominant kernel's roofline, the
-    CPU baseline and GFLOP/s against n per routine (best trans case for
-    dgemm), kept short enough to be read whole (about 1.5 KB)."""
+                 single, nxt, potrf_top=None):
+    """The one stdout line: the headline, the dominant kernel's roofline (and
+    the largest dpotrf order's, which led the kernel time before), the CPU
+    baseline and GFLOP/s against n per routine (best trans case for dgemm),
+    kept short enough to be read whole (about 1.7 KB)."""
     def best_gemm(n):
         return max(per_size[f"dgemm_{t}_n{n}"]["gflops"] for t in ("NN", "NT", "TN", "TT"))
     out = dict(head)
@@ -799,6 +800,9 @@ def compact_line(head, args, restore_bytes, peak_frac, roofline, cpu, per_size, 
     out["fp64_peak_frac"] = peak_frac
     out["roofline"] = {k: roofline[k] for k in ("bound", "achieved", "peak", "unit", "frac",
                                                 "traffic", "kernel", "avg_launch_ms")}
+    if potrf_top is not None and potrf_top["kernel"] != roofline["kernel"]:
+        out["roofline_dpotrf_largest"] = {k: potrf_top[k] for k in (
+            "kernel", "bound", "achieved", "unit", "frac", "traffic", "avg_launch_ms")}
     if cpu is not None:
         out["cpu_baseline"] = {"value": round(cpu["value"], 2), "unit": cpu["unit"],
                                "cores": cpu["cores"], "kind": "oracle",
@@ -853,6 +857,9 @@ def main():
                     help="plan execution modes timed on the uneven batch")
     ap.add_argument("--riccati-only", action="store_true",
                     help="only the Riccati recursion workload (profiling)")
+    ap.add_argument("--next-parts", type=str, default="uneven,backward,riccati",
+                    help="with --next-only: which of the uneven batch, differentiation and "
+                         "Riccati workloads run (profiling one workload at a time)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -893,10 +900,15 @@ def main():
               flush=True)
         return
     if args.next_only:
-        nxt = {"uneven_batch": uneven_batch(torch, _lib, inputs, args.steps,
-                                            args.uneven_modes.split(","))}
-        nxt["backward"] = backward_workload(torch, _lib, inputs, args.steps)
-        nxt["riccati"] = riccati_workload(torch, _lib, inputs, args.steps)
+        parts = args.next_parts.split(",")
+        nxt = {}
+        if "uneven" in parts:
+            nxt["uneven_batch"] = uneven_batch(torch, _lib, inputs, args.steps,
+                                               args.uneven_modes.split(","))
+        if "backward" in parts:
+            nxt["backward"] = backward_workload(torch, _lib, inputs, args.steps)
+        if "riccati" in parts:
+            nxt["riccati"] = riccati_workload(torch, _lib, inputs, args.steps)
         if args.skinny:
             nxt["skinny"] = skinny_sweeps(torch, _lib, inputs, args.steps)
         print(json.dumps({"next": nxt}), flush=True)
@@ -1015,6 +1027,15 @@ def main():
                 "algorithmic_bytes_per_launch": d["bytes_per_launch"],
                 "algorithmic_flops_per_launch": d["flops_per_launch"],
                 "avg_launch_ms": d["avg_launch_ms"]}
+    potrf_top = None
+    if args.potrf_sizes:
+        pk = _lib.dpotrf_kernel_name(max(args.potrf_sizes))
+        if pk in kernels:
+            p = kernels[pk]
+            potrf_top = {"kernel": pk, "bound": p["bound"], "achieved": p["achieved"],
+                         "unit": p["unit"], "frac": p["frac"],
+                         "traffic": traffic_for(pk, p["bytes_per_launch"]),
+                         "avg_launch_ms": p["avg_launch_ms"]}
 
     parity = None
     single = None
@@ -1066,6 +1087,7 @@ def main():
         },
         "fp64_peak_frac": round(value / (PEAK_FP64_TFLOPS * 1e3), 4),
         "roofline": roofline,
+        "roofline_dpotrf_largest": potrf_top,
         "ceilings": ceil,
         "cpu_baseline": cpu,
         "kernels": kernels,
@@ -1081,7 +1103,7 @@ def main():
     print(f"[bench] details {blob}", file=sys.stderr, flush=True)
 
     line = compact_line(head, args, restore[0] / args.steps, details["fp64_peak_frac"], roofline,
-                        cpu, per_size, ceil, parity, single, nxt)
+                        cpu, per_size, ceil, parity, single, nxt, potrf_top)
     print(line, flush=True)
 
 

@@ -47,8 +47,11 @@ def test_compact_line_is_short_and_complete():
     head = {"metric": bench.METRIC, "value": 24567.8, "unit": "GFLOP/s", "n_gpus": 1,
             "steps": 20, "warmup": 5, "ms_per_step": 18.6543, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
-    roof = {"bound": "mfma", "achieved": 21.96, "peak": 78.6, "unit": "TFLOP/s", "frac": 0.2794,
-            "traffic": 5327000000.0, "kernel": "potrf_nt16", "avg_launch_ms": 1.0433}
+    roof = {"bound": "mfma", "achieved": 45.93, "peak": 78.6, "unit": "TFLOP/s", "frac": 0.5843,
+            "traffic": 1467363519, "kernel": "gemm_packed_tile64_k16_db_TT",
+            "avg_launch_ms": 0.4791}
+    potrf_top = {"kernel": "potrf_nt16", "bound": "mfma", "achieved": 24.36, "unit": "TFLOP/s",
+                 "frac": 0.3099, "traffic": 5340990465, "avg_launch_ms": 0.9402}
     cpu = {"value": 45.123456, "unit": "GFLOP/s", "cores": 128, "seconds": 12.345,
            "value_1_thread": 4.456, "cpu_model": "AMD EPYC 9575F 64-Core Processor"}
     ceil = {"hbm_read_gbps": 6123.4, "hbm_copy_gbps": 5432.1, "hbm_3r1w_gbps": 5678.9}
@@ -58,7 +61,7 @@ def test_compact_line_is_short_and_complete():
     nxt = {"uneven_batch": {"modes": {"fused_graph": {"best_ms": 1.5234}},
                             "speedup_vs": {"grouped": 270.1, "grouped_graph": 280.2}}}
     line = bench.compact_line(head, args, 0.0, 0.3125, roof, cpu, per_size, ceil, parity, single,
-                              nxt)
+                              nxt, potrf_top)
     assert "\n" not in line and len(line) <= 2048, len(line)
     rec = json.loads(line)
     for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
@@ -66,6 +69,7 @@ def test_compact_line_is_short_and_complete():
         assert key in rec, key
     assert "workload" in rec["config"]
     assert set(rec["roofline"]) >= {"bound", "achieved", "peak", "unit", "frac", "traffic"}
+    assert rec["roofline_dpotrf_largest"]["kernel"] == "potrf_nt16"
     assert set(rec["cpu_baseline"]) >= {"value", "unit", "cores", "kind", "sample"}
     assert rec["cpu_baseline"]["kind"] == "oracle"
     assert len(rec["gflops_vs_n"]["dgemm_best_trans"]) == len(sizes)
