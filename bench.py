@@ -623,7 +623,7 @@ def backward_workload(torch, _lib, inputs, reps):
     aby = batch * (8.0 * n * (n + 1) + 8.0 * n * n)
     roof = min(PEAK_FP64_TFLOPS, afl / aby * PEAK_HBM_GBS / 1e3)
     out["adjoint_kernel_n64_batch8192"] = {
-        "kernel": "potrf_adj_kernel", "ms": round(a_best, 4), "median_ms": round(a_med, 4),
+        "kernel": "potrf_adj_regs_kernel<4>", "ms": round(a_best, 4), "median_ms": round(a_med, 4),
         "flops": afl, "algorithmic_bytes": aby, "gflops": round(afl / a_best / 1e6, 1),
         "gbps": round(aby / a_best / 1e6, 1), "roofline_tflops": round(roof, 2),
         "roof_frac": round(afl / a_best / 1e9 / roof, 3)}

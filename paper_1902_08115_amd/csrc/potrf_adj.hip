@@ -22,10 +22,35 @@ __global__ __launch_bounds__(ADJ_IPB * 64) void potrf_adj_kernel(PotrfAdjArgs p)
                    smem[inst], lane);
 }
 
+// Orders up to 64: every tile in registers (potrf_adj_regs), one kernel per
+// tile count.
+template <int NT>
+__global__ __launch_bounds__(ADJ_IPB * 64) void potrf_adj_regs_kernel(PotrfAdjArgs p)
+{
+    __shared__ AdjSmem smem[ADJ_IPB];
+    const int lane = threadIdx.x & 63;
+    const int inst = threadIdx.x >> 6;
+    const int64_t b = (int64_t)blockIdx.x * ADJ_IPB + inst;
+    if (b >= p.batch)
+        return;
+    const double *L = inst_ptr(p.L, p.Larr, p.sL, b);
+    const double *Lb = inst_ptr(p.Lbar, p.Lbararr, p.sLbar, b);
+    double *Ab = inst_ptr(p.Abar, p.Abararr, p.sAbar, b);
+    potrf_adj_regs<NT>(L, (size_t)p.ldl, Lb, (size_t)p.ldlb, Ab, (size_t)p.ldab, p.n, smem[inst],
+                       lane);
+}
+
 hipError_t launch_potrf_adj(const PotrfAdjArgs &a, hipStream_t s)
 {
     const int64_t blocks = ((int64_t)a.batch + ADJ_IPB - 1) / ADJ_IPB;
-    hipLaunchKernelGGL(potrf_adj_kernel, dim3((unsigned)blocks), dim3(64 * ADJ_IPB), 0, s, a);
+    const dim3 grid((unsigned)blocks), block(64 * ADJ_IPB);
+    switch ((a.n + 15) / 16) {
+    case 1: hipLaunchKernelGGL(potrf_adj_regs_kernel<1>, grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(potrf_adj_regs_kernel<2>, grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(potrf_adj_regs_kernel<3>, grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL(potrf_adj_regs_kernel<4>, grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL(potrf_adj_kernel, grid, block, 0, s, a); break;
+    }
     return hipGetLastError();
 }
 

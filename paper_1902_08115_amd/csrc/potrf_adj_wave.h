@@ -238,4 +238,103 @@ __device__ __forceinline__ void potrf_adj_wave(const double *Lp, size_t ldl, con
     }
 }
 
+// The same adjoint for orders up to 16 NT (NT <= 4) with every tile in
+// registers: L^T and Lbar^T are read once (coalesced, transposed through
+// LDS), P and Z never leave the registers, the diagonal inverses are formed
+// once for both solves, and Abar is written once -- no fences, no tile read
+// back.  Tile indices are compile-time constants (NT is a template
+// parameter), so the tile arrays are registers; tiles past the order are
+// zero, the diagonal tiles of L padded with the identity.
+template <int NT>
+__device__ __forceinline__ void potrf_adj_regs(const double *Lp, size_t ldl, const double *Lbp,
+                                               size_t ldlb, double *Ap, size_t lda, int n,
+                                               AdjSmem &S, int lane)
+{
+    const MB_GLOBAL double *L = global_ptr(Lp);
+    const MB_GLOBAL double *Lb = global_ptr(Lbp);
+    MB_GLOBAL double *Ab = global_ptr(Ap);
+    const int lr = lane & 15, lg = lane >> 4;
+    const d4 zero = d4{0.0, 0.0, 0.0, 0.0};
+    d4 LT[NT][NT];  // LT[K][I] = L(K,I)^T, K >= I
+#pragma unroll
+    for (int I = 0; I < NT; ++I)
+#pragma unroll
+        for (int K = I; K < NT; ++K)
+            LT[K][I] = adj_ldt(L, ldl, n, 16 * I, 16 * K, K == I, K == I, S, lane);
+
+    // P(I,J) = Phi( sum_{K>=I} L(K,I)^T Lbar(K,J) ), I >= J, into Z
+    d4 Z[NT][NT];
+#pragma unroll
+    for (int J = 0; J < NT; ++J) {
+        d4 LbT[NT];
+#pragma unroll
+        for (int K = J; K < NT; ++K)
+            LbT[K] = adj_ldt(Lb, ldlb, n, 16 * J, 16 * K, K == J, false, S, lane);
+#pragma unroll
+        for (int I = J; I < NT; ++I) {
+            d4 acc = zero;
+#pragma unroll
+            for (int K = I; K < NT; ++K)
+                acc = adj_xyT(acc, LT[K][I], LbT[K], 1.0);
+            if (I == J) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = lg + 4 * r;
+                    acc[r] = c > lr ? 0.0 : (c == lr ? 0.5 * acc[r] : acc[r]);
+                }
+            }
+            Z[I][J] = acc;
+        }
+    }
+
+    // L_JJ^{-T}, once for both solves
+    d4 WT[NT];
+#pragma unroll
+    for (int J = 0; J < NT; ++J)
+        WT[J] = adj_transpose(adj_inv_lower(adj_transpose(LT[J][J], S, lane), lane), S, lane);
+
+    // Z L = P: Z(I,J) = (P(I,J) - sum_{J<K<=I} Z(I,K) L(K,J)) L_JJ^{-1}
+#pragma unroll
+    for (int J = NT - 1; J >= 0; --J) {
+#pragma unroll
+        for (int I = J; I < NT; ++I) {
+            d4 acc = Z[I][J];
+#pragma unroll
+            for (int K = J + 1; K <= I; ++K)
+                acc = adj_xyT(acc, Z[I][K], LT[K][J], -1.0);
+            Z[I][J] = adj_xyT(zero, acc, WT[J], 1.0);
+        }
+    }
+
+    // W L = Z^T: W(I,J) = (Z(J,I)^T - sum_{K>J} W(I,K) L(K,J)) L_JJ^{-1}
+    d4 W[NT][NT];
+#pragma unroll
+    for (int J = NT - 1; J >= 0; --J) {
+#pragma unroll
+        for (int I = 0; I < NT; ++I) {
+            d4 acc = I <= J ? adj_transpose(Z[J][I], S, lane) : zero;
+#pragma unroll
+            for (int K = J + 1; K < NT; ++K)
+                acc = adj_xyT(acc, W[I][K], LT[K][J], -1.0);
+            W[I][J] = adj_xyT(zero, acc, WT[J], 1.0);
+        }
+    }
+
+    // Abar = (W + W^T) / 2, each block and its mirror stored in their own order
+#pragma unroll
+    for (int J = 0; J < NT; ++J) {
+#pragma unroll
+        for (int I = J; I < NT; ++I) {
+            const d4 b = adj_transpose(W[J][I], S, lane);
+            d4 s;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                s[r] = 0.5 * (W[I][J][r] + b[r]);
+            adj_st(Ab, lda, n, 16 * I, 16 * J, false, s, lr, lg);
+            if (I != J)
+                adj_st(Ab, lda, n, 16 * J, 16 * I, false, adj_transpose(s, S, lane), lr, lg);
+        }
+    }
+}
+
 }  // namespace mb
