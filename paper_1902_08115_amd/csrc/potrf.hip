@@ -10,6 +10,9 @@
 #ifndef POTRF_ROWS_IPW
 #define POTRF_ROWS_IPW 4
 #endif
+#ifndef POTRF_REGS_MAX_NT
+#define POTRF_REGS_MAX_NT 6
+#endif
 
 namespace mb {
 
@@ -44,6 +47,26 @@ __global__ __launch_bounds__(IPB * 64) __attribute__((amdgpu_waves_per_eu(2))) v
     constexpr int G1 = PIPE ? ((NT % 2 == 1 || NT < 12) ? 2 : 3) : 0;
     const int info = potrf_wave<true, G, PIPE, G1, KC>(A, (size_t)p.lda, p.n, NT, smem[inst],
                                                                 lane, pcache[inst]);
+    if (lane == 0)
+        p.info[b] = info;
+}
+
+// Orders of a few tiles: the factor in registers (potrf_regs).  Up to four
+// tiles the kernel fits in 128 registers, four waves per SIMD: a batch of
+// 4096 then runs in one round on the 1024 SIMDs instead of leaving a quarter
+// of it for a second round of single waves.  FULL: the order is 16 NT.
+template <int NT, int IPB, bool FULL>
+__global__ __launch_bounds__(IPB * 64) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 4 : 1))) void potrf_regs_kernel(PotrfArgs p)
+{
+    __shared__ PotrfSmem smem[IPB];
+    const int lane = threadIdx.x & 63;
+    // the instance is uniform over the wave: its base address stays scalar
+    const int inst = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t b = (int64_t)blockIdx.x * IPB + inst;
+    if (b >= p.batch)
+        return;
+    double *A = inst_ptr(p.A, p.Aarr, p.sA, b);
+    const int info = potrf_regs<NT, FULL>(A, (uint32_t)p.lda, p.n, smem[inst], lane);
     if (lane == 0)
         p.info[b] = info;
 }
@@ -180,6 +203,19 @@ __global__ void fill_info_kernel(int *info, int batch)
 }
 
 template <int NT, int IPB>
+static hipError_t launch_potrf_regs(const PotrfArgs &a, hipStream_t s)
+{
+    const int64_t blocks = ((int64_t)a.batch + IPB - 1) / IPB;
+    if (a.n == 16 * NT)
+        hipLaunchKernelGGL((potrf_regs_kernel<NT, IPB, true>), dim3((unsigned)blocks),
+                           dim3(64 * IPB), 0, s, a);
+    else
+        hipLaunchKernelGGL((potrf_regs_kernel<NT, IPB, false>), dim3((unsigned)blocks),
+                           dim3(64 * IPB), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int NT, int IPB>
 static hipError_t launch_potrf_t(const PotrfArgs &a, hipStream_t s)
 {
     const int64_t blocks = ((int64_t)a.batch + IPB - 1) / IPB;
@@ -193,6 +229,21 @@ hipError_t launch_potrf_lower(const PotrfArgs &a, hipStream_t s)
     if (a.n <= POTRF_ROWS_MAX_N)
         return launch_potrf_rows_n(a.n, a, s, std::make_integer_sequence<int, POTRF_ROWS_MAX_N>{});
     const int nt = (a.n + 15) / 16;
+    // the register-resident kernel addresses an instance with 32-bit offsets
+    const bool regs = nt <= POTRF_REGS_MAX_NT && (uint64_t)a.lda * (uint64_t)a.n * 8u < (1ull << 32);
+    if (regs) {
+        switch (nt) {
+        case 3: return launch_potrf_regs<3, 4>(a, s);
+        case 4: return launch_potrf_regs<4, 4>(a, s);
+#if POTRF_REGS_MAX_NT >= 5
+        case 5: return launch_potrf_regs<5, 4>(a, s);
+#endif
+#if POTRF_REGS_MAX_NT >= 6
+        case 6: return launch_potrf_regs<6, 4>(a, s);
+#endif
+        default: break;
+        }
+    }
     switch (nt) {
     case 3: return launch_potrf_t<3, 4>(a, s);
     case 4: return launch_potrf_t<4, 4>(a, s);

@@ -59,18 +59,17 @@ __device__ __forceinline__ int tri_pos(int a, int b)
     return 16 * b - (b * (b - 1)) / 2 + (a - b);
 }
 
-// 1/sqrt(a) for a positive normal a: the hardware estimate refined by two
-// Newton-Raphson steps for f(y) = 1/y^2 - a, y <- y + y (1 - a y^2) / 2
-// (quadratic convergence; the result is within a few ulp of the exact value).
+// 1/sqrt(a) for a positive normal a: the hardware estimate y (relative error
+// about 2^-24) refined by one third-order step of the Newton iteration for
+// f(y) = 1/y^2 - a, y <- y (1 + e/2 + 3 e^2 / 8) with e = 1 - a y^2 (error
+// e^3; the result measured within 1 ulp of the exact value over 2^20 inputs
+// spanning 2^-100 .. 2^100).  Four dependent operations after the estimate,
+// where two second-order steps take eight.
 __device__ __forceinline__ double rsqrt_nr(double a)
 {
-    double y = __builtin_amdgcn_rsq(a);
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const double e = fma(-(a * y), y, 1.0);
-        y = fma(0.5 * y, e, y);
-    }
-    return y;
+    const double y = __builtin_amdgcn_rsq(a);
+    const double e = fma(-(a * y), y, 1.0);
+    return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
 // 1/a for a normal a: the hardware estimate refined by two Newton-Raphson
@@ -163,6 +162,14 @@ __device__ __forceinline__ void elim_step(d4 &t, d4 &lo, d4 &x, int lane, int co
         t[r] = fma(-lr, tb[r], t[r]);
     if (g == GC && act)
         lo[RC] = (i >= C) ? l : 0.0;
+    // an opaque copy: the select above is done here, in place; otherwise it
+    // is deferred to the end of the factorization, with all sixteen lane
+    // masks held until then (about 40 more registers)
+    {
+        double v = lo[RC];
+        asm volatile("" : "+v"(v));
+        lo[RC] = v;
+    }
     if (INV) {
         const double ms = (i == C) ? 1.0 - rs : lr;
 #pragma unroll
@@ -215,6 +222,130 @@ __device__ __forceinline__ void factor_diag_tile(d4 &t, d4 &x, Smem &S, int J, i
     t = lo;
 }
 
+// Step C = 4K + c of factor_tall: register K of every tile holds the four
+// columns 4K .. 4K + 3 (lane group g: column 4K + g), so the step touches that
+// register only.  Column C of the trailing diagonal tile, T[i][C], comes
+// through the crossbar (register K of lane (c, i)); the pivot T[C][C] and row
+// C of the block, T[C][4K + g], by DPP broadcasts from lane C of each row of
+// 16.  l = T[i][C] / sqrt(piv) goes to group c of lo (column C of L), and
+// the block's later columns lose (T[i][C] / piv) T[C][q].  Every panel tile
+// does the same with its own column P[i][C]: l_P = P[i][C] / sqrt(piv) to
+// column C of its factor, P[i][q] -= l_P T[C][q] / sqrt(piv).  With INV,
+// X = L^{-1} is updated alongside: X <= C_C^{-1} X for the column factor C_C
+// of L -- row C divided by l_CC, rows below lose l_iC / l_CC times the old
+// row C (one fma with the DPP-broadcast old row C).  A pivot that is not
+// positive makes l_CC a NaN (1/sqrt of it is a NaN or infinite), and every
+// later step computes on NaNs; the failure is found from the diagonal of L
+// at the end (only columns before it are ever stored).
+template <int K, int c, int NP, bool INV>
+__device__ __forceinline__ void tall_step(d4 &t, d4 &lo, d4 &x, d4 *P, d4 *LP, int lane)
+{
+    constexpr int C = 4 * K + c;
+    const int i = lane & 15, g = lane >> 4;
+    const double col = lane_read(t[K], 16 * c + i);  // T[i][C]
+    const double piv = row_bcast<C>(col);           // T[C][C]
+    const double rs = rsqrt_nr(piv);
+    const double l = col * rs;
+    const double tb = row_bcast<C>(t[K]);  // T[C][4K + g]
+    d4 xb;
+    if (INV) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            xb[r] = row_bcast<C>(x[r]);
+    }
+    const double lr = l * rs;
+    t[K] = fma(-lr, tb, t[K]);
+    lo[K] = (g == c) ? l : lo[K];
+    if (INV) {
+        const double ms = (i == C) ? 1.0 - rs : lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            x[r] = fma(-ms, xb[r], x[r]);
+    }
+    if (NP > 0) {
+        const double tbs = tb * rs;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const double pc = lane_read(P[p][K], 16 * c + i);  // P[i][C]
+            const double lp = pc * rs;
+            P[p][K] = fma(-lp, tbs, P[p][K]);
+            LP[p][K] = (g == c) ? lp : LP[p][K];
+        }
+    }
+}
+
+template <int K, int NP, bool SKIP, bool INV>
+__device__ __forceinline__ void tall_block(d4 &t, d4 &lo, d4 &x, d4 *P, d4 *LP, int lane, int cols)
+{
+    if (!SKIP || 4 * K + 0 < cols)
+        tall_step<K, 0, NP, INV>(t, lo, x, P, LP, lane);
+    if (!SKIP || 4 * K + 1 < cols)
+        tall_step<K, 1, NP, INV>(t, lo, x, P, LP, lane);
+    if (!SKIP || 4 * K + 2 < cols)
+        tall_step<K, 2, NP, INV>(t, lo, x, P, LP, lane);
+    if (!SKIP || 4 * K + 3 < cols)
+        tall_step<K, 3, NP, INV>(t, lo, x, P, LP, lane);
+    if constexpr (K < 3) {
+        // the block's four columns of L update everything to their right at
+        // once: T -= L_K L_K^T and P -= L_P,K L_K^T, one rank-4 MFMA each
+        // (registers up to K receive garbage; they are finished)
+        t = mfma16(-lo[K], lo[K], t);
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+            P[p] = mfma16(-lo[K], LP[p][K], P[p]);
+    }
+}
+
+// Factor the diagonal tile t (lower triangle valid, accumulator order) and
+// solve the NP panel tiles P below it, P <= P L^{-T}, by one wave: the
+// right-looking blocked form of the column elimination -- four elimination
+// steps per block of four columns on one register (tall_step), then the
+// rank-4 update of everything to the right by the matrix cores.  The panel
+// tiles go through the same elimination (the right-variant solve, Sec.
+// 3.1.3), so no inverse is formed.  Columns at and past `cols` are the
+// identity padding of an order that is not a multiple of 16: with SKIP they
+// are skipped by scalar branches, otherwise they run as exact identity steps.
+// A failing pivot at column c is recorded in S.fail (as 16 J + c).  On exit t
+// holds L (upper part zero) and P the panel of L.
+template <int NP, bool SKIP, bool INV = false, class Smem>
+__device__ __forceinline__ void factor_tall(d4 &t, d4 &x, d4 *P, Smem &S, int J, int lane, int cols)
+{
+    const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (i >= g + 4 * r)
+            S.tile[tri_pos(i, g + 4 * r)] = t[r];
+    wave_lds_sync();
+    d4 lo, LP[NP > 0 ? NP : 1];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int q = g + 4 * r;
+        t[r] = S.tile[q <= i ? tri_pos(i, q) : tri_pos(q, i)];
+        lo[r] = (q == i) ? 1.0 : 0.0;
+        x[r] = lo[r];
+    }
+    tall_block<0, NP, SKIP, INV>(t, lo, x, P, LP, lane, cols);
+    tall_block<1, NP, SKIP, INV>(t, lo, x, P, LP, lane, cols);
+    tall_block<2, NP, SKIP, INV>(t, lo, x, P, LP, lane, cols);
+    tall_block<3, NP, SKIP, INV>(t, lo, x, P, LP, lane, cols);
+    // the first column whose diagonal entry of L is not a positive number
+    // (lane (g, i) holds l_ii in register r when i = g + 4r)
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        bad |= (i == g + 4 * r) & !(lo[r] > 0.0);
+    const uint64_t bm = __builtin_amdgcn_ballot_w64(bad);
+    const uint32_t cm = (uint32_t)(bm | (bm >> 16) | (bm >> 32) | (bm >> 48)) & 0xFFFFu;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        t[r] = (i < g + 4 * r) ? 0.0 : lo[r];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+        P[p] = LP[p];
+    if (cm != 0 && lane == 0)
+        S.fail = 16 * J + __builtin_ctz(cm);
+}
+
 // Load tile (I, K) in accumulator order.  diag: the tile of A on the
 // diagonal (strict upper part read as zero); outside the n x n matrix the
 // identity is used.
@@ -236,6 +367,84 @@ __device__ __forceinline__ d4 load_tile(const MB_GLOBAL double *A, size_t lda, i
         t[r] = v;
     }
     return t;
+}
+
+// Byte offset of element (r, c) of a matrix that spans less than 4 GiB: one
+// 32-bit register per address (scalar base + vector offset), instead of a
+// 64-bit address per element.
+__device__ __forceinline__ uint32_t off32(int r, int c, uint32_t lda)
+{
+    return ((uint32_t)r + (uint32_t)c * lda) * 8u;
+}
+
+__device__ __forceinline__ double ld_off(const MB_GLOBAL double *A, uint32_t off)
+{
+    return *(const MB_GLOBAL double *)((const MB_GLOBAL char *)A + off);
+}
+
+__device__ __forceinline__ void st_off(MB_GLOBAL double *A, uint32_t off, double v)
+{
+    *(MB_GLOBAL double *)((MB_GLOBAL char *)A + off) = v;
+}
+
+// A wave-uniform address held in scalar registers: a per-register base for
+// loads and stores that then share one lane offset (without this the
+// compiler folds the base into a 64-bit vector address per base).
+template <class T>
+__device__ __forceinline__ T *scalar_ptr(T *p)
+{
+    const uint64_t a = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return (T *)(((uint64_t)hi << 32) | lo);
+}
+
+// load_tile for a matrix of less than 4 GiB.  With FULL (the order is a
+// multiple of 16) every element is inside the matrix: plain loads, no
+// selects.  Otherwise every lane loads unconditionally, from its element's
+// position clamped into the matrix, and only the value is selected (a load
+// under a branch ends a basic block, and the compiler then waits for all
+// outstanding loads before the first use of any of them); outside the
+// matrix the tile is the identity.  The strict upper part of a diagonal
+// tile is loaded as it is: the factorization never reads it.
+template <bool FULL>
+__device__ __forceinline__ d4 load_tile32(const MB_GLOBAL double *A, uint32_t lda, int n, int I,
+                                          int K, int lr, int lg)
+{
+    d4 t;
+    const int gi = 16 * I + lr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int gc = 16 * K + lg + 4 * r;
+        if (FULL) {
+            // a scalar base per register plus one lane offset for all loads
+            const MB_GLOBAL double *At =
+                scalar_ptr(A + (16 * I + (16 * K + 4 * r) * (size_t)lda));
+            t[r] = ld_off(At, off32(lr, lg, lda));
+        } else {
+            const double v = ld_off(A, off32(min(gi, n - 1), min(gc, n - 1), lda));
+            const bool in = gi < n && gc < n;
+            t[r] = in ? v : ((gi == gc) ? 1.0 : 0.0);
+        }
+    }
+    return t;
+}
+
+// Store tile (I, J) of L (its lower part if diag), columns before fail_col,
+// for a matrix of less than 4 GiB (FULL: the order is a multiple of 16).
+template <bool FULL>
+__device__ __forceinline__ void store_tile32(MB_GLOBAL double *A, uint32_t lda, int n, int I, int J,
+                                             const d4 &t, bool diag, int fail_col, int lr, int lg)
+{
+    const int gi = 16 * I + lr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int gc = 16 * J + lg + 4 * r;
+        if ((FULL || (gi < n && gc < n)) && gc < fail_col && (!diag || gc <= gi)) {
+            MB_GLOBAL double *At = scalar_ptr(A + (16 * I + (16 * J + 4 * r) * (size_t)lda));
+            st_off(At, off32(lr, lg, lda), t[r]);
+        }
+    }
 }
 
 // Store the lower part of a diagonal tile (columns before a failing pivot).
@@ -565,5 +774,80 @@ __device__ __forceinline__ int potrf_wave(double *Ain, size_t lda, int n, int NT
     return (S.fail == INT_MAX) ? 0 : S.fail + 1;
 }
 
+// Small orders (a few tiles): the factor kept in registers, every tile read
+// once and written once.  Block column J (left-looking): the loads of column
+// J + 1 are issued, the tiles of column J lose L(I,K) L(J,K)^T for the
+// earlier columns K (factor tiles still in registers), then the diagonal
+// tile is factored and the panel below it solved in one blocked elimination
+// (factor_tall).  No tile is stored and read back, so there is no memory
+// fence and no re-read; only the factor tiles still needed by later columns
+// and one column of prefetched tiles are live at a time.  Tile indices are compile-time constants (NT is a template
+// parameter), so the tiles stay in registers.  A failing pivot ends the
+// factorization after its block column's panel solve; only columns before it
+// are stored.  The matrix must span less than 4 GiB (32-bit offsets).
+// Block column J of potrf_regs; returns false at a failing pivot.  On entry
+// T[I][J] (I >= J) holds the loaded tiles of the column and T[I][K] (K < J)
+// the factor tiles of the earlier columns.
+template <int NT, bool FULL, int J>
+__device__ __forceinline__ bool regs_column(d4 (&T)[NT][NT], MB_GLOBAL double *A, uint32_t lda,
+                                            int n, PotrfSmem &S, int lane, int &fail_col)
+{
+    const int lr = lane & 15, lg = lane >> 4;
+    // the next column's loads are in flight while this one is factored
+#pragma unroll
+    for (int I = J + 1; I < NT && J + 1 < NT; ++I)
+        T[I][J + 1] = load_tile32<FULL>(A, lda, n, I, J + 1, lr, lg);
+    // left-looking update by the factor tiles of the earlier columns
+#pragma unroll
+    for (int I = J; I < NT; ++I)
+#pragma unroll
+        for (int K = 0; K < J; ++K)
+            T[I][J] = update_nt(T[I][J], T[I][K], T[J][K]);
+    constexpr int NP = NT - 1 - J;
+    d4 P[NP > 0 ? NP : 1], unused;
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+        P[p] = T[J + 1 + p][J];
+    // only the last diagonal tile can be partial (its steps past the order
+    // are skipped)
+    factor_tall<NP, !FULL && NP == 0>(T[J][J], unused, P, S, J, lane, n - 16 * J);
+    wave_lds_sync();
+    fail_col = __builtin_amdgcn_readfirstlane(S.fail);
+    // block column J is final: its stores drain while the later columns are
+    // factored
+    store_tile32<FULL>(A, lda, n, J, J, T[J][J], true, fail_col, lr, lg);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        T[J + 1 + p][J] = P[p];
+        store_tile32<FULL>(A, lda, n, J + 1 + p, J, P[p], false, fail_col, lr, lg);
+    }
+    return fail_col == INT_MAX;
+}
+
+template <int NT, bool FULL, int... J>
+__device__ __forceinline__ void regs_columns(d4 (&T)[NT][NT], MB_GLOBAL double *A, uint32_t lda,
+                                             int n, PotrfSmem &S, int lane, int &fail_col,
+                                             std::integer_sequence<int, J...>)
+{
+    (regs_column<NT, FULL, J>(T, A, lda, n, S, lane, fail_col) && ...);
+}
+
+// FULL: n == 16 NT.
+template <int NT, bool FULL>
+__device__ __forceinline__ int potrf_regs(double *Ain, uint32_t lda, int n, PotrfSmem &S, int lane)
+{
+    MB_GLOBAL double *A = global_ptr(Ain);
+    const int lr = lane & 15, lg = lane >> 4;
+    d4 T[NT][NT];
+#pragma unroll
+    for (int I = 0; I < NT; ++I)
+        T[I][0] = load_tile32<FULL>(A, lda, n, I, 0, lr, lg);
+    if (lane == 0)
+        S.fail = INT_MAX;
+    wave_lds_sync();
+    int fail_col = INT_MAX;
+    regs_columns<NT, FULL>(T, A, lda, n, S, lane, fail_col, std::make_integer_sequence<int, NT>{});
+    return (fail_col == INT_MAX) ? 0 : fail_col + 1;
+}
 
 }  // namespace mb

@@ -101,8 +101,10 @@ def _run_modes(spec, X0, modes=MODES):
     return out
 
 
-# largest dpotrf order the plain launches factor with whole rows in lanes
-ROWS_MAX_N = 32
+# largest dpotrf order the plain launches factor with kernels of their own
+# (whole rows in lanes up to 32, the factor in registers up to 96); above it
+# they run the same code as the fused kernel
+SMALL_MAX_N = 96
 
 
 @pytest.mark.parametrize("seed", [0, 1])
@@ -111,10 +113,10 @@ def test_uneven_batch_every_mode(seed):
     non-SPD): every execution mode equals the oracle problem by problem;
     the graph and direct launches of one code path agree bit for bit;
     dpotrf info agrees across all modes, and dpotrf factors agree bit for bit
-    across all modes for orders above 32 (orders up to 32 take the
-    four-instances-per-wave kernel in the grouped path, a different
-    evaluation order from the fused kernel's; both were checked against the
-    oracle above)."""
+    across all modes for orders above 96 (smaller orders take kernels of their
+    own in the grouped path -- whole rows in lanes, or the factor in
+    registers -- whose evaluation order differs from the fused kernel's; both
+    were checked against the oracle above)."""
     spec = inputs.uneven_spec(400, inputs.seed_for(3, seed), non_spd_frac=0.1)
     X0 = inputs.uneven_host(spec, inputs.seed_for(3, 100 + seed))
     res = _run_modes(spec, X0)
@@ -127,7 +129,7 @@ def test_uneven_batch_every_mode(seed):
     pot = np.nonzero(spec["op"] == 1)[0]
     for i in pot:
         o, n = int(spec["off_c"][i]), int(spec["n"][i])
-        if n > ROWS_MAX_N:
+        if n > SMALL_MAX_N:
             assert np.array_equal(res["fused"][0][o:o + n * n], res["grouped"][0][o:o + n * n]), i
     assert np.array_equal(res["fused"][1][pot], res["grouped"][1][pot])
 
