@@ -230,15 +230,13 @@ __device__ __forceinline__ void factor_diag_tile(d4 &t, d4 &x, Smem &S, int J, i
 // 16.  l = T[i][C] / sqrt(piv) goes to group c of lo (column C of L), and
 // the block's later columns lose (T[i][C] / piv) T[C][q].  Every panel tile
 // does the same with its own column P[i][C]: l_P = P[i][C] / sqrt(piv) to
-// column C of its factor, P[i][q] -= l_P T[C][q] / sqrt(piv).  With INV,
-// X = L^{-1} is updated alongside: X <= C_C^{-1} X for the column factor C_C
-// of L -- row C divided by l_CC, rows below lose l_iC / l_CC times the old
-// row C (one fma with the DPP-broadcast old row C).  A pivot that is not
-// positive makes l_CC a NaN (1/sqrt of it is a NaN or infinite), and every
-// later step computes on NaNs; the failure is found from the diagonal of L
-// at the end (only columns before it are ever stored).
-template <int K, int c, int NP, bool INV>
-__device__ __forceinline__ void tall_step(d4 &t, d4 &lo, d4 &x, d4 *P, d4 *LP, int lane)
+// column C of its factor, P[i][q] -= l_P T[C][q] / sqrt(piv).  A pivot that
+// is not positive makes l_CC a NaN (1/sqrt of it is a NaN or infinite), and
+// every later step computes on NaNs; the failure is found from the diagonal
+// of L at the end (only columns before it are ever stored; the columns of L
+// and of the panel factors before it never mix with the NaNs).
+template <int K, int c, int NP>
+__device__ __forceinline__ void tall_step(d4 &t, d4 &lo, d4 *P, d4 *LP, int lane)
 {
     constexpr int C = 4 * K + c;
     const int i = lane & 15, g = lane >> 4;
@@ -247,21 +245,8 @@ __device__ __forceinline__ void tall_step(d4 &t, d4 &lo, d4 &x, d4 *P, d4 *LP, i
     const double rs = rsqrt_nr(piv);
     const double l = col * rs;
     const double tb = row_bcast<C>(t[K]);  // T[C][4K + g]
-    d4 xb;
-    if (INV) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            xb[r] = row_bcast<C>(x[r]);
-    }
-    const double lr = l * rs;
-    t[K] = fma(-lr, tb, t[K]);
+    t[K] = fma(-(l * rs), tb, t[K]);
     lo[K] = (g == c) ? l : lo[K];
-    if (INV) {
-        const double ms = (i == C) ? 1.0 - rs : lr;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            x[r] = fma(-ms, xb[r], x[r]);
-    }
     if (NP > 0) {
         const double tbs = tb * rs;
 #pragma unroll
@@ -274,17 +259,17 @@ __device__ __forceinline__ void tall_step(d4 &t, d4 &lo, d4 &x, d4 *P, d4 *LP, i
     }
 }
 
-template <int K, int NP, bool SKIP, bool INV>
-__device__ __forceinline__ void tall_block(d4 &t, d4 &lo, d4 &x, d4 *P, d4 *LP, int lane, int cols)
+template <int K, int NP, bool SKIP>
+__device__ __forceinline__ void tall_block(d4 &t, d4 &lo, d4 *P, d4 *LP, int lane, int cols)
 {
     if (!SKIP || 4 * K + 0 < cols)
-        tall_step<K, 0, NP, INV>(t, lo, x, P, LP, lane);
+        tall_step<K, 0, NP>(t, lo, P, LP, lane);
     if (!SKIP || 4 * K + 1 < cols)
-        tall_step<K, 1, NP, INV>(t, lo, x, P, LP, lane);
+        tall_step<K, 1, NP>(t, lo, P, LP, lane);
     if (!SKIP || 4 * K + 2 < cols)
-        tall_step<K, 2, NP, INV>(t, lo, x, P, LP, lane);
+        tall_step<K, 2, NP>(t, lo, P, LP, lane);
     if (!SKIP || 4 * K + 3 < cols)
-        tall_step<K, 3, NP, INV>(t, lo, x, P, LP, lane);
+        tall_step<K, 3, NP>(t, lo, P, LP, lane);
     if constexpr (K < 3) {
         // the block's four columns of L update everything to their right at
         // once: T -= L_K L_K^T and P -= L_P,K L_K^T, one rank-4 MFMA each
@@ -307,8 +292,8 @@ __device__ __forceinline__ void tall_block(d4 &t, d4 &lo, d4 &x, d4 *P, d4 *LP, 
 // are skipped by scalar branches, otherwise they run as exact identity steps.
 // A failing pivot at column c is recorded in S.fail (as 16 J + c).  On exit t
 // holds L (upper part zero) and P the panel of L.
-template <int NP, bool SKIP, bool INV = false, class Smem>
-__device__ __forceinline__ void factor_tall(d4 &t, d4 &x, d4 *P, Smem &S, int J, int lane, int cols)
+template <int NP, bool SKIP, class Smem>
+__device__ __forceinline__ void factor_tall(d4 &t, d4 *P, Smem &S, int J, int lane, int cols)
 {
     const int i = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -322,12 +307,11 @@ __device__ __forceinline__ void factor_tall(d4 &t, d4 &x, d4 *P, Smem &S, int J,
         const int q = g + 4 * r;
         t[r] = S.tile[q <= i ? tri_pos(i, q) : tri_pos(q, i)];
         lo[r] = (q == i) ? 1.0 : 0.0;
-        x[r] = lo[r];
     }
-    tall_block<0, NP, SKIP, INV>(t, lo, x, P, LP, lane, cols);
-    tall_block<1, NP, SKIP, INV>(t, lo, x, P, LP, lane, cols);
-    tall_block<2, NP, SKIP, INV>(t, lo, x, P, LP, lane, cols);
-    tall_block<3, NP, SKIP, INV>(t, lo, x, P, LP, lane, cols);
+    tall_block<0, NP, SKIP>(t, lo, P, LP, lane, cols);
+    tall_block<1, NP, SKIP>(t, lo, P, LP, lane, cols);
+    tall_block<2, NP, SKIP>(t, lo, P, LP, lane, cols);
+    tall_block<3, NP, SKIP>(t, lo, P, LP, lane, cols);
     // the first column whose diagonal entry of L is not a positive number
     // (lane (g, i) holds l_ii in register r when i = g + 4r)
     bool bad = false;
@@ -804,13 +788,13 @@ __device__ __forceinline__ bool regs_column(d4 (&T)[NT][NT], MB_GLOBAL double *A
         for (int K = 0; K < J; ++K)
             T[I][J] = update_nt(T[I][J], T[I][K], T[J][K]);
     constexpr int NP = NT - 1 - J;
-    d4 P[NP > 0 ? NP : 1], unused;
+    d4 P[NP > 0 ? NP : 1];
 #pragma unroll
     for (int p = 0; p < NP; ++p)
         P[p] = T[J + 1 + p][J];
     // only the last diagonal tile can be partial (its steps past the order
     // are skipped)
-    factor_tall<NP, !FULL && NP == 0>(T[J][J], unused, P, S, J, lane, n - 16 * J);
+    factor_tall<NP, !FULL && NP == 0>(T[J][J], P, S, J, lane, n - 16 * J);
     wave_lds_sync();
     fail_col = __builtin_amdgcn_readfirstlane(S.fail);
     // block column J is final: its stores drain while the later columns are
