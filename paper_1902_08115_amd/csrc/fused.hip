@@ -70,8 +70,21 @@ __device__ __forceinline__ void run_task(const FusedTask &t, TaskSmem &S, int la
         MB_FUSED_CASE(14, true, false, 2, 2)
         MB_FUSED_CASE(15, true, true, 2, 2)
     case FUSED_POTRF: {
-        const int info =
-            potrf_wave<true>(t.C, (size_t)t.ldc, t.n, (t.n + 15) / 16, S.potrf, lane);
+        // up to four tiles the factor stays in registers (potrf_regs, as the
+        // plain launches; its 32-bit offsets need an instance below 4 GiB)
+        const int nt = (t.n + 15) / 16;
+        const bool regs = (uint64_t)t.ldc * (uint64_t)t.n * 8u < (1ull << 32);
+        int info;
+        if (regs && nt == 1)
+            info = potrf_regs<1, false>(t.C, (uint32_t)t.ldc, t.n, S.potrf, lane);
+        else if (regs && nt == 2)
+            info = potrf_regs<2, false>(t.C, (uint32_t)t.ldc, t.n, S.potrf, lane);
+        else if (regs && nt == 3)
+            info = potrf_regs<3, false>(t.C, (uint32_t)t.ldc, t.n, S.potrf, lane);
+        else if (regs && nt == 4)
+            info = potrf_regs<4, false>(t.C, (uint32_t)t.ldc, t.n, S.potrf, lane);
+        else
+            info = potrf_wave<true>(t.C, (size_t)t.ldc, t.n, nt, S.potrf, lane);
         if (lane == 0)
             *global_ptr(t.info) = info;
         break;
@@ -147,7 +160,7 @@ __device__ __forceinline__ FusedTask task_unpack(int v)
 // the dpotrf class and the others on the dgemm class, so that both kinds run
 // side by side instead of one phase after the other; a wave whose class is
 // drained everywhere moves on to the other class.
-__global__ __launch_bounds__(FUSED_WAVES * 64) void fused_kernel(const FusedTask *tasks,
+__global__ __launch_bounds__(FUSED_WAVES * 64) __attribute__((amdgpu_waves_per_eu(2))) void fused_kernel(const FusedTask *tasks,
                                                                  const int *qoff, int *counters,
                                                                  int potrf_waves)
 {
