@@ -365,6 +365,231 @@ __global__ __launch_bounds__(RIC_WPB * 64) void riccati_small_kernel(RiccatiArgs
         info[q] = -1;
 }
 
+// ---- m up to 64, nx up to 48: every stage in registers -------------------------
+// One wave per problem, no workspace: per stage the dtrmm result C (NTM x
+// NTX tiles), the matrix M = RSQ + C C^T (its lower NTM (NTM + 1) / 2 tiles)
+// and the factor live in registers, so nothing is stored and read back
+// within a stage; F is written once, column block by column block, and
+// the next stage reads the factor's bottom-right block Lc back once (L2-hot,
+// coalesced, transposed through LDS).  The tile counts are template
+// parameters: every tile index is a constant.
+
+// Y[i][c] = X(16T + c, 16K + i) for the nx x nx lower matrix X (zero above
+// the diagonal and outside nx): tile (T, K) loaded in its own order -- every
+// lane loads from its element's position clamped into the matrix (a 32-bit
+// offset from the scalar base), the value selected -- and transposed
+// through LDS.
+__device__ __forceinline__ d4 ric_lower_t(const MB_GLOBAL double *X, uint32_t ld, int nx, int T,
+                                          int K, RicSmallSmem &S, int lane)
+{
+    const int i = lane & 15, g = lane >> 4;
+    const int row = 16 * T + i;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int col = 16 * K + g + 4 * r;
+        const double v = ld_off(X, off32(min(row, nx - 1), min(col, nx - 1), ld));
+        S.t[i][g + 4 * r] = (row < nx && col < nx && row >= col) ? v : 0.0;
+    }
+    wave_lds_sync();
+    d4 y;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        y[r] = S.t[g + 4 * r][i];
+    wave_lds_sync();
+    return y;
+}
+
+// Tile (I, T) of the rows x cols matrix X, zero outside it; unconditional
+// clamped loads (32-bit offsets from the scalar base), the value selected.
+__device__ __forceinline__ d4 ric_rect(const MB_GLOBAL double *X, uint32_t ld, int rows, int cols,
+                                       int I, int T, int lr, int lg)
+{
+    d4 t;
+    const int gi = 16 * I + lr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int gc = 16 * T + lg + 4 * r;
+        const double v = ld_off(X, off32(min(gi, rows - 1), min(gc, cols - 1), ld));
+        t[r] = (gi < rows && gc < cols) ? v : 0.0;
+    }
+    return t;
+}
+
+// Factor the n x n matrix held in T (lower tiles; NT = ceil(n / 16)) in
+// registers, left-looking (as potrf_regs), writing the lower triangle of the
+// factor to X column block by column block.  Returns the LAPACK info.
+template <int NT, int J>
+__device__ __forceinline__ bool ric_column(d4 (&T)[NT][NT], MB_GLOBAL double *X, uint32_t ld, int n,
+                                           PotrfSmem &S, int lane, int &fail_col)
+{
+    const int lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int I = J; I < NT; ++I)
+#pragma unroll
+        for (int K = 0; K < J; ++K)
+            T[I][J] = update_nt(T[I][J], T[I][K], T[J][K]);
+    constexpr int NP = NT - 1 - J;
+    d4 P[NP > 0 ? NP : 1];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+        P[p] = T[J + 1 + p][J];
+    factor_tall<NP, NP == 0>(T[J][J], P, S, J, lane, n - 16 * J);
+    wave_lds_sync();
+    fail_col = __builtin_amdgcn_readfirstlane(S.fail);
+    store_tile32<false>(X, ld, n, J, J, T[J][J], true, fail_col, lr, lg);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        T[J + 1 + p][J] = P[p];
+        store_tile32<false>(X, ld, n, J + 1 + p, J, P[p], false, fail_col, lr, lg);
+    }
+    return fail_col == INT_MAX;
+}
+
+template <int NT, int... J>
+__device__ __forceinline__ int ric_factor(d4 (&T)[NT][NT], MB_GLOBAL double *X, uint32_t ld, int n,
+                                          PotrfSmem &S, int lane, std::integer_sequence<int, J...>)
+{
+    if (lane == 0)
+        S.fail = INT_MAX;
+    wave_lds_sync();
+    int fail_col = INT_MAX;
+    (ric_column<NT, J>(T, X, ld, n, S, lane, fail_col) && ...);
+    return (fail_col == INT_MAX) ? 0 : fail_col + 1;
+}
+
+template <int NTM, int NTX>
+__global__ __launch_bounds__(RIC_WPB * 64) void riccati_regs_kernel(RiccatiArgs p)
+{
+    __shared__ RicSmallSmem smem[RIC_WPB];
+    const int lane0 = threadIdx.x & 63;
+    // the problem is uniform over the wave: its addresses stay scalar
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t b = (int64_t)blockIdx.x * RIC_WPB + wave;
+    if (b >= p.batch)
+        return;
+    RicSmallSmem &S = smem[wave];
+    const int nx = p.nx, nu = p.nu, N = p.N, m = nx + nu;
+    MB_GLOBAL int *info = global_ptr(p.info) + b * (N + 1);
+    MB_GLOBAL double *LN = global_ptr(p.LN) + b * p.sL;
+    int st;
+    {
+        const int lane = lane0;
+        const int lr = lane & 15, lg = lane >> 4;
+        // terminal factor Lc_N = chol(Q_N)
+        const MB_GLOBAL double *QN = global_ptr(p.QN) + b * p.sQ;
+        d4 T[NTX][NTX];
+#pragma unroll
+        for (int I = 0; I < NTX; ++I)
+#pragma unroll
+            for (int K = 0; K <= I; ++K)
+                T[I][K] = ric_rect(QN, (uint32_t)p.ldq, nx, nx, I, K, lr, lg);
+        st = ric_factor<NTX>(T, LN, (uint32_t)p.ldl, nx, S.potrf, lane,
+                             std::make_integer_sequence<int, NTX>{});
+    }
+    if (lane0 == 0)
+        info[N] = st;
+    int n = N - 1;
+    const MB_GLOBAL double *Lc = LN;
+    uint32_t ldlc = (uint32_t)p.ldl;
+    for (; st == 0 && n >= 0; --n) {
+        const MB_GLOBAL double *BAt = global_ptr(p.BAt) + b * p.sBAt + n * p.stBAt;
+        const MB_GLOBAL double *RSQ = global_ptr(p.RSQ) + b * p.sRSQ + n * p.stRSQ;
+        MB_GLOBAL double *F = global_ptr(p.F) + b * p.sF + n * p.stF;
+        // an opaque copy of the lane index per stage: the element offsets and
+        // masks derived from it are formed where they are used instead of
+        // being hoisted out of the stage loop (all of them, held in registers
+        // for the whole recursion)
+        int lane = lane0;
+        asm volatile("" : "+v"(lane));
+        const int lr = lane & 15, lg = lane >> 4;
+        // the previous factor's stores are complete before it is read back
+        wave_mem_sync();
+        d4 Y[NTX][NTX];  // Y[T][K] = Lc(T, K)^T, T >= K
+#pragma unroll
+        for (int K = 0; K < NTX; ++K)
+#pragma unroll
+            for (int T = K; T < NTX; ++T)
+                Y[T][K] = ric_lower_t(Lc, ldlc, nx, T, K, S, lane);
+        // C = BAt Lc
+        d4 C[NTM][NTX];
+#pragma unroll
+        for (int I = 0; I < NTM; ++I) {
+            d4 x[NTX];
+#pragma unroll
+            for (int T = 0; T < NTX; ++T)
+                x[T] = ric_rect(BAt, (uint32_t)p.ldbat, m, nx, I, T, lr, lg);
+#pragma unroll
+            for (int K = 0; K < NTX; ++K) {
+                d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int T = K; T < NTX; ++T)
+                    acc = add_xyT(acc, x[T], Y[T][K]);
+                C[I][K] = acc;
+            }
+            // one row of tiles at a time: the scheduler would otherwise hoist
+            // every load of the stage, and their registers, to the top
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // M = RSQ + C C^T (lower tiles)
+        d4 M[NTM][NTM];
+#pragma unroll
+        for (int I = 0; I < NTM; ++I)
+#pragma unroll
+            for (int J = 0; J <= I; ++J) {
+                d4 acc = ric_rect(RSQ, (uint32_t)p.ldrsq, m, m, I, J, lr, lg);
+#pragma unroll
+                for (int K = 0; K < NTX; ++K)
+                    acc = add_xyT(acc, C[I][K], C[J][K]);
+                M[I][J] = acc;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        st = ric_factor<NTM>(M, F, (uint32_t)p.ldf, m, S.potrf, lane,
+                             std::make_integer_sequence<int, NTM>{});
+        if (lane == 0)
+            info[n] = st;
+        Lc = F + (size_t)nu + (size_t)nu * (size_t)p.ldf;
+        ldlc = (uint32_t)p.ldf;
+    }
+    // stages below a failure are not computed
+    for (int q = lane0; q <= n; q += 64)
+        info[q] = -1;
+}
+
+// The register-resident kernel's shapes (its 32-bit offsets need every
+// operand instance below 4 GiB).
+static bool riccati_regs(const RiccatiArgs &a)
+{
+    const int m = a.nx + a.nu;
+    const auto fits = [](int ld, int cols) { return (uint64_t)ld * (uint64_t)cols * 8u < (1ull << 32); };
+    return m > 16 && m <= 64 && a.nx >= 1 && a.nx <= 48 && fits(a.ldf, m) && fits(a.ldl, a.nx) &&
+           fits(a.ldbat, a.nx) && fits(a.ldrsq, m) && fits(a.ldq, a.nx);
+}
+
+template <int NTM, int NTX>
+static void launch_riccati_regs_t(const RiccatiArgs &a, hipStream_t s)
+{
+    const int64_t blocks = (a.batch + RIC_WPB - 1) / RIC_WPB;
+    hipLaunchKernelGGL((riccati_regs_kernel<NTM, NTX>), dim3((unsigned)blocks), dim3(RIC_WPB * 64),
+                       0, s, a);
+}
+
+static hipError_t launch_riccati_regs(const RiccatiArgs &a, hipStream_t s)
+{
+    const int ntm = (a.nx + a.nu + 15) / 16, ntx = (a.nx + 15) / 16;
+    switch (ntm * 4 + ntx) {
+    case 2 * 4 + 1: launch_riccati_regs_t<2, 1>(a, s); break;
+    case 2 * 4 + 2: launch_riccati_regs_t<2, 2>(a, s); break;
+    case 3 * 4 + 1: launch_riccati_regs_t<3, 1>(a, s); break;
+    case 3 * 4 + 2: launch_riccati_regs_t<3, 2>(a, s); break;
+    case 3 * 4 + 3: launch_riccati_regs_t<3, 3>(a, s); break;
+    case 4 * 4 + 1: launch_riccati_regs_t<4, 1>(a, s); break;
+    case 4 * 4 + 2: launch_riccati_regs_t<4, 2>(a, s); break;
+    case 4 * 4 + 3: launch_riccati_regs_t<4, 3>(a, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 int64_t riccati_slot_doubles(int nx, int nu)
 {
     const int64_t ntm = (nx + nu + 15) / 16, ntx = (nx + 15) / 16;
@@ -406,6 +631,8 @@ hipError_t launch_riccati(const RiccatiArgs &a, int waves, hipStream_t s)
                            a);
         return hipGetLastError();
     }
+    if (riccati_regs(a))
+        return launch_riccati_regs(a, s);
     const unsigned blocks = (unsigned)((waves + RIC_WPB - 1) / RIC_WPB);
     if (riccati_lds(a.nx, a.nu))
         hipLaunchKernelGGL(riccati_kernel<RIC_LDS_TILES>, dim3(blocks), dim3(RIC_WPB * 64), 0, s, a,
