@@ -365,7 +365,7 @@ __global__ __launch_bounds__(RIC_WPB * 64) void riccati_small_kernel(RiccatiArgs
         info[q] = -1;
 }
 
-// ---- m up to 64, nx up to 48: every stage in registers -------------------------
+// ---- m up to 96, nx up to 64: every stage in registers -------------------------
 // One wave per problem, no workspace: per stage the dtrmm result C (NTM x
 // NTX tiles), the matrix M = RSQ + C C^T (its lower NTM (NTM + 1) / 2 tiles)
 // and the factor live in registers, so nothing is stored and read back
@@ -556,12 +556,13 @@ __global__ __launch_bounds__(RIC_WPB * 64) void riccati_regs_kernel(RiccatiArgs 
 }
 
 // The register-resident kernel's shapes (its 32-bit offsets need every
-// operand instance below 4 GiB).
+// operand instance below 4 GiB).  At six by four tiles it holds 381
+// registers: one wave per SIMD, still faster than the workspace kernel.
 static bool riccati_regs(const RiccatiArgs &a)
 {
     const int m = a.nx + a.nu;
     const auto fits = [](int ld, int cols) { return (uint64_t)ld * (uint64_t)cols * 8u < (1ull << 32); };
-    return m > 16 && m <= 64 && a.nx >= 1 && a.nx <= 48 && fits(a.ldf, m) && fits(a.ldl, a.nx) &&
+    return m > 16 && m <= 96 && a.nx >= 1 && a.nx <= 64 && fits(a.ldf, m) && fits(a.ldl, a.nx) &&
            fits(a.ldbat, a.nx) && fits(a.ldrsq, m) && fits(a.ldq, a.nx);
 }
 
@@ -585,6 +586,15 @@ static hipError_t launch_riccati_regs(const RiccatiArgs &a, hipStream_t s)
     case 4 * 4 + 1: launch_riccati_regs_t<4, 1>(a, s); break;
     case 4 * 4 + 2: launch_riccati_regs_t<4, 2>(a, s); break;
     case 4 * 4 + 3: launch_riccati_regs_t<4, 3>(a, s); break;
+    case 5 * 4 + 1: launch_riccati_regs_t<5, 1>(a, s); break;
+    case 5 * 4 + 2: launch_riccati_regs_t<5, 2>(a, s); break;
+    case 5 * 4 + 3: launch_riccati_regs_t<5, 3>(a, s); break;
+    case 5 * 4 + 4: launch_riccati_regs_t<5, 4>(a, s); break;
+    case 6 * 4 + 1: launch_riccati_regs_t<6, 1>(a, s); break;
+    case 6 * 4 + 2: launch_riccati_regs_t<6, 2>(a, s); break;
+    case 6 * 4 + 3: launch_riccati_regs_t<6, 3>(a, s); break;
+    case 6 * 4 + 4: launch_riccati_regs_t<6, 4>(a, s); break;
+    case 4 * 4 + 4: launch_riccati_regs_t<4, 4>(a, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
