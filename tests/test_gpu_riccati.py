@@ -72,11 +72,13 @@ def _run(nx, nu, N, BAt, RSQ, QN, F, LN, info, work=None):
 @pytest.mark.parametrize("nx,nu,N,batch", [
     (8, 4, 10, 7), (24, 12, 10, 5), (40, 20, 4, 3), (64, 32, 3, 2),
     (1, 1, 4, 9), (5, 0, 3, 4), (17, 9, 5, 3), (3, 2, 1, 6), (6, 3, 0, 5), (16, 16, 2, 3),
-    (33, 15, 2, 2), (0, 4, 3, 3),
+    (33, 15, 2, 2), (0, 4, 3, 3), (70, 10, 2, 2), (50, 60, 2, 2),
 ])
 def test_riccati_vs_oracle(nx, nu, N, batch):
     """Every stage of every problem, shapes spanning several 16 x 16 tiles with
-    ragged edges, nu = 0, nx = 0, N = 0 and N = 1."""
+    ragged edges, nu = 0, nx = 0, N = 0 and N = 1; every kernel of the
+    recursion (one tile up to m = 16, registers up to m = 96 and nx = 64, the
+    workspace kernel beyond: (70, 10) and (50, 60))."""
     torch, _lib, blas = torch_mods()
     m = nx + nu
     say(f"riccati nx={nx} nu={nu} N={N} batch={batch}")
