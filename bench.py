@@ -85,6 +85,18 @@ def source_digest(paths):
     return h.hexdigest()[:16]
 
 
+def riccati_kernel_label(nx, nu):
+    """The kernel the library runs for a Riccati shape (csrc/riccati.hip)."""
+    m = nx + nu
+    if m <= 16:
+        return "riccati_small_kernel"
+    if m <= 96 and 1 <= nx <= 64:
+        return f"riccati_regs_kernel<{(m + 15) // 16},{(nx + 15) // 16}>"
+    if ((m + 15) // 16) * ((nx + 15) // 16) <= 6:
+        return "riccati_kernel<6> (C in LDS)"
+    return "riccati_kernel<0> (C in the workspace)"
+
+
 def traffic_for(kernel, per_launch_bytes):
     """HBM traffic measured with rocprofv3 counters for this kernel, if the
     committed measurement was taken on the current kernel sources."""
@@ -726,9 +738,7 @@ def riccati_workload(torch, _lib, inputs, reps, composed=True):
                "gflops": round(fl / best / 1e6, 1), "gbps": round(by / best / 1e6, 1),
                "roof_frac": round((fl / best / 1e9) / min(PEAK_FP64_TFLOPS,
                                                           fl / by * PEAK_HBM_GBS / 1e3), 3),
-               "kernel": "riccati_small_kernel" if nx + nu <= 16 else (
-                   "riccati_kernel<6> (C in LDS)" if ((nx + nu + 15) // 16) * ((nx + 15) // 16) <= 6
-                   else "riccati_kernel<0> (C in the workspace)"),
+               "kernel": riccati_kernel_label(nx, nu),
                "flops_per_recursion": riccati_flops(nx, nu, N),
                "bytes_per_recursion": riccati_bytes(nx, nu, N),
                "paper_blasfeo_api_c_haswell_s_per_recursion": PAPER_RICCATI_S[(nx, nu)]}
