@@ -54,8 +54,9 @@ def test_sweep_sizes_with_failing_instance(si, n):
         assert d <= POTRF_TOL, d
 
 
-@pytest.mark.parametrize("n", list(range(1, 33)) + [33, 47, 64, 65, 90, 100, 128, 129, 150, 176,
-                                                  185, 200, 224, 237, 256, 272, 288, 300, 304])
+@pytest.mark.parametrize("n", list(range(1, 33)) + [33, 47, 48, 64, 65, 80, 90, 96, 100, 128, 129,
+                                                  150, 176, 185, 200, 224, 237, 256, 272, 288, 300,
+                                                  304])
 def test_exact_integer_factor(n):
     """A = L0 L0^T with integer L0 (diagonal in {1,2,4}): the factor is L0
     exactly for any evaluation order, so the GPU result must match bit for bit.
@@ -135,6 +136,42 @@ def test_info_rows_orders_every_column(n):
             Lrj, Lgj = Lr.T[:n, :j], Ag[b].T[:n, :j]
             d = np.linalg.norm((Lgj - Lrj)[low]) / np.linalg.norm(Lrj[low])
             assert d <= POTRF_TOL, (b, j, d)
+        assert np.isnan(Ag[b].T[:n, :n][np.triu_indices(n, 1)]).all(), "upper touched"
+        assert np.array_equal(Ag[b][:, n:], A[b][:, n:], equal_nan=True), "padding touched"
+
+
+@pytest.mark.parametrize("n", [40, 48, 64, 80, 96])
+def test_info_regs_orders_every_column(n):
+    """Orders 33..96, the factor held in registers (orders 16 NT with scalar
+    tile bases, others with clamped loads and a partial last tile): a_jj = -1
+    in instance j for every column j, plus one SPD instance; strictly upper
+    triangle NaN and padded ld.  info is j+1 in instance j, the columns
+    before j match the oracle's partial factor (a failing pivot turns the
+    later columns to NaN in registers; none of them may be stored), the upper
+    triangle and the padding are never written."""
+    import oracle
+    g = inputs.rng(8190 + n)
+    batch = n + 1
+    ld = n + 3
+    A = inputs.spd_batch(g, batch, n, ld=ld, upper_value=np.nan)
+    for j in range(n):
+        A[j, j, j] = -1.0
+    say(f"dpotrf info regs n={n}")
+    Ag, info = _run(n, A, batch)
+    assert list(info) == list(range(1, n + 1)) + [0], info
+    for b in range(batch):
+        Lr = np.ascontiguousarray(A[b:b + 1]).ravel().copy()
+        want = b + 1 if b < n else 0
+        assert oracle.dpotrf_l_raw(n, Lr, ld) == want
+        j = b if b < n else n
+        Lr = Lr.reshape(A[b:b + 1].shape)[0]
+        if j > 0:
+            low = np.tril(np.ones((n, j), dtype=bool))
+            Lrj, Lgj = Lr.T[:n, :j], Ag[b].T[:n, :j]
+            d = np.linalg.norm((Lgj - Lrj)[low]) / np.linalg.norm(Lrj[low])
+            assert d <= POTRF_TOL, (b, j, d)
+        # columns from the failing one on keep their input values
+        assert np.array_equal(Ag[b].T[:n, j:], A[b].T[:n, j:], equal_nan=True), "failed columns written"
         assert np.isnan(Ag[b].T[:n, :n][np.triu_indices(n, 1)]).all(), "upper touched"
         assert np.array_equal(Ag[b][:, n:], A[b][:, n:], equal_nan=True), "padding touched"
 
