@@ -10,9 +10,6 @@
 #ifndef POTRF_ROWS_IPW
 #define POTRF_ROWS_IPW 4
 #endif
-#ifndef POTRF_REGS_MAX_NT
-#define POTRF_REGS_MAX_NT 6
-#endif
 
 namespace mb {
 
@@ -54,7 +51,9 @@ __global__ __launch_bounds__(IPB * 64) __attribute__((amdgpu_waves_per_eu(2))) v
 // Orders of a few tiles: the factor in registers (potrf_regs).  Up to four
 // tiles the kernel fits in 128 registers, four waves per SIMD: a batch of
 // 4096 then runs in one round on the 1024 SIMDs instead of leaving a quarter
-// of it for a second round of single waves.  FULL: the order is 16 NT.
+// of it for a second round of single waves.  FULL: the order is 16 NT.  At 8
+// tiles only the FULL form is used (one more register set would halve the
+// waves per SIMD).
 template <int NT, int IPB, bool FULL>
 __global__ __launch_bounds__(IPB * 64) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 4 : 1))) void potrf_regs_kernel(PotrfArgs p)
 {
@@ -229,18 +228,20 @@ hipError_t launch_potrf_lower(const PotrfArgs &a, hipStream_t s)
     if (a.n <= POTRF_ROWS_MAX_N)
         return launch_potrf_rows_n(a.n, a, s, std::make_integer_sequence<int, POTRF_ROWS_MAX_N>{});
     const int nt = (a.n + 15) / 16;
-    // the register-resident kernel addresses an instance with 32-bit offsets
-    const bool regs = nt <= POTRF_REGS_MAX_NT && (uint64_t)a.lda * (uint64_t)a.n * 8u < (1ull << 32);
+    // the register-resident kernel up to 7 tiles, and at 8 tiles for the
+    // order 128 (two waves per SIMD; a partial eighth tile needs one more
+    // register set and one wave per SIMD, where it measured slower than
+    // potrf_lower); it addresses an instance with 32-bit offsets
+    const bool regs = (nt <= 7 || a.n == 128) &&
+                      (uint64_t)a.lda * (uint64_t)a.n * 8u < (1ull << 32);
     if (regs) {
         switch (nt) {
         case 3: return launch_potrf_regs<3, 4>(a, s);
         case 4: return launch_potrf_regs<4, 4>(a, s);
-#if POTRF_REGS_MAX_NT >= 5
         case 5: return launch_potrf_regs<5, 4>(a, s);
-#endif
-#if POTRF_REGS_MAX_NT >= 6
         case 6: return launch_potrf_regs<6, 4>(a, s);
-#endif
+        case 7: return launch_potrf_regs<7, 4>(a, s);
+        case 8: return launch_potrf_regs<8, 4>(a, s);
         default: break;
         }
     }

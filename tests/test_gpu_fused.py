@@ -102,9 +102,9 @@ def _run_modes(spec, X0, modes=MODES):
 
 
 # largest dpotrf order the plain launches factor with kernels of their own
-# (whole rows in lanes up to 32, the factor in registers up to 96); above it
-# they run the same code as the fused kernel
-SMALL_MAX_N = 96
+# (whole rows in lanes up to 32, the factor in registers up to 112 and at
+# 128); above it they run the same code as the fused kernel
+SMALL_MAX_N = 128
 
 
 @pytest.mark.parametrize("seed", [0, 1])
@@ -113,7 +113,7 @@ def test_uneven_batch_every_mode(seed):
     non-SPD): every execution mode equals the oracle problem by problem;
     the graph and direct launches of one code path agree bit for bit;
     dpotrf info agrees across all modes, and dpotrf factors agree bit for bit
-    across all modes for orders above 96 (smaller orders take kernels of their
+    across all modes for orders above 128 (smaller orders take kernels of their
     own in the grouped path -- whole rows in lanes, or the factor in
     registers -- whose evaluation order differs from the fused kernel's; both
     were checked against the oracle above)."""
