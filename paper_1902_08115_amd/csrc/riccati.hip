@@ -466,6 +466,7 @@ __global__ __launch_bounds__(RIC_WPB * 64) void riccati_regs_kernel(RiccatiArgs 
     // 2.63 against 2.98, (64,32) 7.42 against 7.78; hoisted (40,20) 3.02
     // against 3.47.
     constexpr bool PIN = !(NTM == 4 && NTX == 3);
+    constexpr bool PRE = NTM >= 6;
     __shared__ RicSmallSmem smem[RIC_WPB];
     const int lane0 = threadIdx.x & 63;
     // the problem is uniform over the wave: its addresses stay scalar
@@ -508,6 +509,18 @@ __global__ __launch_bounds__(RIC_WPB * 64) void riccati_regs_kernel(RiccatiArgs 
         int lane = lane0;
         asm volatile("" : "+v"(lane));
         const int lr = lane & 15, lg = lane >> 4;
+        // PRE: the stage's RSQ tiles are loaded first, into M, so that their
+        // latency overlaps the fence and the dtrmm (at six row tiles, one
+        // wave per SIMD, where nothing else hides it)
+        d4 M[NTM][NTM];
+        if constexpr (PRE) {
+#pragma unroll
+            for (int I = 0; I < NTM; ++I)
+#pragma unroll
+                for (int J = 0; J <= I; ++J)
+                    M[I][J] = ric_rect(RSQ, (uint32_t)p.ldrsq, m, m, I, J, lr, lg);
+            __builtin_amdgcn_sched_barrier(0);
+        }
         // the previous factor's stores are complete before it is read back
         wave_mem_sync();
         d4 Y[NTX][NTX];  // Y[T][K] = Lc(T, K)^T, T >= K
@@ -536,12 +549,11 @@ __global__ __launch_bounds__(RIC_WPB * 64) void riccati_regs_kernel(RiccatiArgs 
                 __builtin_amdgcn_sched_barrier(0);
         }
         // M = RSQ + C C^T (lower tiles)
-        d4 M[NTM][NTM];
 #pragma unroll
         for (int I = 0; I < NTM; ++I)
 #pragma unroll
             for (int J = 0; J <= I; ++J) {
-                d4 acc = ric_rect(RSQ, (uint32_t)p.ldrsq, m, m, I, J, lr, lg);
+                d4 acc = PRE ? M[I][J] : ric_rect(RSQ, (uint32_t)p.ldrsq, m, m, I, J, lr, lg);
 #pragma unroll
                 for (int K = 0; K < NTX; ++K)
                     acc = add_xyT(acc, C[I][K], C[J][K]);
