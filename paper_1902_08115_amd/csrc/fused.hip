@@ -70,8 +70,12 @@ __device__ __forceinline__ void run_task(const FusedTask &t, TaskSmem &S, int la
         MB_FUSED_CASE(14, true, false, 2, 2)
         MB_FUSED_CASE(15, true, true, 2, 2)
     case FUSED_POTRF: {
-        // up to four tiles the factor stays in registers (potrf_regs, as the
-        // plain launches; its 32-bit offsets need an instance below 4 GiB)
+        // up to five tiles the factor stays in registers (potrf_regs, as the
+        // plain launches; its 32-bit offsets need an instance below 4 GiB).
+        // Larger orders take the plain-loop left-looking form.  The kernel
+        // sits at its 256-register cap: this choice spills 20 bytes per lane,
+        // the pipelined loops 92 and the register form also at six and seven
+        // tiles 264 (both measured 1-2% slower on the uneven batch).
         const int nt = (t.n + 15) / 16;
         const bool regs = (uint64_t)t.ldc * (uint64_t)t.n * 8u < (1ull << 32);
         int info;
@@ -83,8 +87,10 @@ __device__ __forceinline__ void run_task(const FusedTask &t, TaskSmem &S, int la
             info = potrf_regs<3, false>(t.C, (uint32_t)t.ldc, t.n, S.potrf, lane);
         else if (regs && nt == 4)
             info = potrf_regs<4, false>(t.C, (uint32_t)t.ldc, t.n, S.potrf, lane);
+        else if (regs && nt == 5)
+            info = potrf_regs<5, false>(t.C, (uint32_t)t.ldc, t.n, S.potrf, lane);
         else
-            info = potrf_wave<true>(t.C, (size_t)t.ldc, t.n, nt, S.potrf, lane);
+            info = potrf_wave<true, 2, false>(t.C, (size_t)t.ldc, t.n, nt, S.potrf, lane);
         if (lane == 0)
             *global_ptr(t.info) = info;
         break;
