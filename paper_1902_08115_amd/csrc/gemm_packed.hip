@@ -49,6 +49,9 @@
 //     one XCD (shared L2).
 #include "mb_internal.h"
 
+#include <cstdint>
+#include <type_traits>
+
 namespace mb {
 
 // Raw buffer resource over a panel (record count just under 2 GiB); an offset
@@ -61,6 +64,12 @@ constexpr int kBufMaxLd = 1 << 21;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const double *p)
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(p), (short)0, 0x7ffffff0,
+                                             0x00020000);
+}
+// The same with a record count of nrec bytes: offsets at or beyond it read as zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc_n(const double *p, unsigned nrec)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(p), (short)0, (int)nrec,
                                              0x00020000);
 }
 __device__ __forceinline__ double buf_ld8(__amdgpu_buffer_rsrc_t r, unsigned off)
@@ -141,9 +150,17 @@ struct Stage {
             const bool in0 = rin && kb + q < k, in1 = rin && kb + q + 1 < k;
             if (!T) {
                 if (BUF) {
-                    const unsigned off = (unsigned)row * 8u + (unsigned)q * ldb;
-                    v[u][0] = buf_ld8(rs, in0 ? off : kOob);
-                    v[u][1] = buf_ld8(rs, in1 ? off + ldb : kOob);
+                    // column q of the panel lies at [q ldb, (q + 1) ldb): the record
+                    // count (k - kb) ldb zeroes the columns past k, so only the
+                    // loop-invariant row test stays in the per-element offset
+                    // (capped at the full record count, which then holds every
+                    // column of the panel: k - kb exceeds it)
+                    const unsigned kr = k - kb > 0 ? (unsigned)(k - kb) : 0u;
+                    const unsigned nrec = kr < 0x7ffffff0u / ldb ? kr * ldb : 0x7ffffff0u;
+                    const __amdgpu_buffer_rsrc_t rk = make_rsrc_n(base, nrec);
+                    const unsigned off = rin ? (unsigned)row * 8u + (unsigned)q * ldb : kOob;
+                    v[u][0] = buf_ld8(rk, off);
+                    v[u][1] = buf_ld8(rk, off + ldb);
                 } else {
                     const double *ptr = base + row + (size_t)q * ld;
                     v[u][0] = ptr_ld8(base, ptr, in0);
@@ -358,10 +375,13 @@ __global__ __launch_bounds__(Cfg::NTHR *Cfg::IPB) void gemm_packed_kernel(GemmAr
 
     // k loop: every panel but the last also stages the next one; the staging
     // loads are issued among the first MFMAs of the panel's first 16 steps.
-    int cur = 0;
     const int klast = ((k - 1) / BK) * BK;
-    for (int kb = 0; kb < klast; kb += BK) {
-        const double *S = &smem[grp][cur][0];
+    // one panel at k offset kb read from LDS buffer CUR (a constant, so the
+    // LDS addresses are immediate offsets); it stages panel kb + BK into the
+    // other buffer (DB == 2) or, after a barrier, into the same one
+    auto panel = [&](int kb, auto curc) __attribute__((always_inline)) {
+        constexpr int CUR = decltype(curc)::value;
+        const double *S = &smem[grp][CUR][0];
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 16) {
             Frags<Cfg> f;
@@ -377,13 +397,30 @@ __global__ __launch_bounds__(Cfg::NTHR *Cfg::IPB) void gemm_packed_kernel(GemmAr
             }
             __builtin_amdgcn_s_setprio(0);
         }
-        const int nxt = (DB == 2) ? (cur ^ 1) : 0;
+        constexpr int NXT = (DB == 2) ? (CUR ^ 1) : 0;
         if constexpr (DB == 1)
             group_sync<WAVE_ONLY>();  // everyone is done reading the single buffer
-        sa.template store<SK>(&smem[grp][nxt][0], tid);
-        sb.template store<SK>(&smem[grp][nxt][Cfg::LDS_A], tid);
+        sa.template store<SK>(&smem[grp][NXT][0], tid);
+        sb.template store<SK>(&smem[grp][NXT][Cfg::LDS_A], tid);
         group_sync<WAVE_ONLY>();
-        cur = nxt;
+    };
+    using B0 = std::integral_constant<int, 0>;
+    using B1 = std::integral_constant<int, 1>;
+    int cur = 0;
+    if constexpr (DB == 2) {
+        // two panels per trip: buffers 0 then 1
+        int kb = 0;
+        for (; kb + BK < klast; kb += 2 * BK) {
+            panel(kb, B0{});
+            panel(kb + BK, B1{});
+        }
+        if (kb < klast) {
+            panel(kb, B0{});
+            cur = 1;
+        }
+    } else {
+        for (int kb = 0; kb < klast; kb += BK)
+            panel(kb, B0{});
     }
 
     // C is needed only by the epilogue: its loads overlap the last panel.

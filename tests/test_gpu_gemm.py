@@ -244,10 +244,12 @@ def test_every_packed_config_exact():
     for cfg in range(_lib.dgemm_config_count()):
         name = _lib.dgemm_config_name(cfg)
         lim = min(300, _lib.dgemm_config_max_mn(cfg))
-        shapes = [(min(lim, 13), min(lim, 9), 37), (lim, lim, 16), (min(lim, 150), min(lim, 70), 45)]
+        # k = 53: an odd number of full panels before the last one (both panel depths)
+        shapes = [(min(lim, 13), min(lim, 9), 37), (lim, lim, 16), (min(lim, 150), min(lim, 70), 45),
+                  (min(lim, 40), min(lim, 33), 53)]
         for trans in TRANS:
             ta, tb = trans
-            for (m, n, k), pad in zip(shapes, (0, 1, 0)):
+            for (m, n, k), pad in zip(shapes, (0, 1, 0, 1)):
                 batch = 2
                 A, B, C = _make(g, ta, tb, m, n, k, batch, pad=pad, gap=1, integer=True)
                 dA, dB, dC = dev(A), dev(B), dev(C)
