@@ -282,7 +282,9 @@ __global__ __launch_bounds__(RIC_WPB * 64) void riccati_kernel(RiccatiArgs p, in
 }
 
 // Problems with m = nu + nx <= 16: every stage is one 16 x 16 tile, and the
-// whole recursion stays in the wave's registers.  The next stage's BAt and
+// whole recursion stays in the wave's registers.  Each stage's tile is
+// factored by the blocked elimination of the register kernels (factor_tall,
+// the columns past the stage's order skipped).  The next stage's BAt and
 // RSQ tiles are loaded while the current stage is factored; the factor of
 // P_n -- needed transposed by the next stage's dtrmm -- goes from the
 // factored tile to the next operand through LDS, so stages exchange nothing
@@ -346,8 +348,8 @@ __global__ __launch_bounds__(RIC_WPB * 64) void riccati_small_kernel(RiccatiArgs
         if (lane == 0)
             S.potrf.fail = INT_MAX;
         wave_lds_sync();
-        d4 w;
-        factor_diag_tile<false, true>(f, w, S.potrf, 0, lane, n == N ? nx : m);
+        d4 P0[1];
+        factor_tall<0, true>(f, P0, S.potrf, 0, lane, n == N ? nx : m);
         wave_lds_sync();
         const int fail = S.potrf.fail;
         const bool term = n == N;
