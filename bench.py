@@ -928,6 +928,14 @@ def main():
     gemm, potrf = build_inputs(torch, inputs, args)
     log("inputs resident")
 
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(torch, oracle, gemm, potrf, args.cpu_flops_per_case)
+        log(f"cpu baseline {cpu['value']:.2f} GFLOP/s on {cpu['cores']} threads "
+            f"({cpu['seconds']} s)")
+
     stream = torch.cuda.current_stream()
     restore = [0]
     for w in range(args.warmup):
@@ -956,16 +964,6 @@ def main():
     hot = potrf_hot(torch, _lib, potrf, stream)
     ceil = ceilings(torch, _lib, stream)
     log(f"ceilings: {ceil}")
-
-    # the oracle on the host runs after the timed steps, so that the warmup and the timed
-    # steps follow the input generation directly
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(torch, oracle, gemm, potrf, args.cpu_flops_per_case)
-        log(f"cpu baseline {cpu['value']:.2f} GFLOP/s on {cpu['cores']} threads "
-            f"({cpu['seconds']} s)")
 
     # per-call and per-kernel-class accounting
     per_size = {}
