@@ -22,6 +22,7 @@ also written to --details-out when given.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -901,6 +902,13 @@ def main():
         total = torch.cuda.get_device_properties(0).total_memory
         room = total - gemm_bytes - per_copy - (24 << 30)
         args.copies = max(1, min(args.steps, room // per_copy))
+
+    # no garbage collection while anything is timed (as timeit does): a full
+    # collection over the interpreter's objects stalls the submitting thread
+    # long enough to drain the launch queue; nothing here depends on cycles
+    # being freed
+    gc.collect()
+    gc.disable()
 
     if args.crossover:
         crossover(torch, _lib, inputs, args)
