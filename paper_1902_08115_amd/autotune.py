@@ -27,6 +27,7 @@ candidate.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -319,6 +320,10 @@ def main():
     ap.add_argument("--keep-within", type=float, default=0.02,
                     help="keep the committed choice when it is this close to the fastest")
     args = ap.parse_args()
+    # no garbage collection inside the timed calls (a full collection stalls
+    # the launching thread and would lengthen one candidate's time)
+    gc.collect()
+    gc.disable()
     if args.fused:
         fused_tune(args)
         return
