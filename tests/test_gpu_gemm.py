@@ -298,6 +298,44 @@ def test_packed_huge_leading_dimension(trans):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("huge", ["A", "B"])
+@pytest.mark.parametrize("config", [5, 15])
+def test_packed_record_count_at_largest_buffer_ld(huge, config):
+    """An operand whose rows are contiguous ('N' A, 'T' B) bounds k by the
+    record count of its panel's buffer resource, (k - kb) ld 8 bytes, capped
+    just under 2 GiB.  At ld = 2^21 (the largest on the buffer path) and
+    k = 200 the full panels take the capped count and the last, partial panel
+    the exact one; the columns past k hold NaN.  Bit-exact on integer data."""
+    torch, _lib, _ = torch_mods()
+    s = torch.cuda.current_stream().cuda_stream
+    ta, tb = ("N", "N") if huge == "A" else ("T", "T")
+    m, n, k = 70, 37, 200
+    g = inputs.rng(7700 + config + (0 if huge == "A" else 1))
+    A, B, C = _make(g, ta, tb, m, n, k, 1, integer=True)
+    ld = 1 << 21
+    X = A if huge == "A" else B
+    rows, cols = X.shape[2], X.shape[1]
+    big = torch.full((cols + 1, ld), float("nan"), dtype=torch.float64, device="cuda")
+    big[:cols, :rows] = torch.from_numpy(X[0]).cuda()
+    dA = big if huge == "A" else dev(A)
+    dB = big if huge == "B" else dev(B)
+    lda = ld if huge == "A" else A.shape[2]
+    ldb = ld if huge == "B" else B.shape[2]
+    dC = dev(C)
+    say(f"dgemm record count ld={ld} huge {huge} {ta}{tb} {m}x{n}x{k} config {config}")
+    st = _lib.dgemm_strided_batched_config(ta, tb, m, n, k, 1.0, dA.data_ptr(), lda,
+                                           A.shape[1] * lda, dB.data_ptr(), ldb,
+                                           B.shape[1] * ldb, -0.5, dC.data_ptr(), C.shape[2],
+                                           C.shape[1] * C.shape[2], 1, config, s)
+    assert st == 0, st
+    Cg = host(dC).reshape(C.shape)
+    Cr = oracle_gemm_batch(ta, tb, m, n, k, 1.0, A, A.shape[2], B, B.shape[2], -0.5, C,
+                           C.shape[2], 1)
+    assert np.array_equal(Cg, Cr, equal_nan=True)
+    del big
+    torch.cuda.empty_cache()
+
+
 SKINNY = [(4, 4, 1), (4, 4, 2), (4, 4, 3), (4, 4, 17), (4, 4, 300), (1, 300, 5), (4, 300, 300),
           (4, 37, 200), (16, 17, 33), (300, 4, 300), (97, 4, 15), (17, 16, 9), (3, 5, 300),
           (16, 16, 257), (33, 2, 64), (2, 3, 8), (4, 4, 12)]
