@@ -135,7 +135,7 @@ struct Stage {
     // Stage the panel at k offset kb; rows r0.. of op(X) with nrows rows and
     // k columns, zero outside.  BUF: 32-bit offsets into a buffer resource
     // based at the panel's origin (ld <= kBufMaxLd); else clamped pointers.
-    template <bool BUF>
+    template <bool BUF, bool KFULL = false>
     __device__ __forceinline__ void load(const double *X, size_t ld, int nrows, int k, int r0,
                                          int kb, int tid)
     {
@@ -147,7 +147,8 @@ struct Stage {
             int row, q;
             coords(tid + u * NTHR, row, q);
             const bool rin = r0 + row < nrows;
-            const bool in0 = rin && kb + q < k, in1 = rin && kb + q + 1 < k;
+            // KFULL: the panel lies wholly inside k (only the row test remains)
+            const bool in0 = rin && (KFULL || kb + q < k), in1 = rin && (KFULL || kb + q + 1 < k);
             if (!T) {
                 if (BUF) {
                     // column q of the panel lies at [q ldb, (q + 1) ldb): the record
@@ -379,8 +380,9 @@ __global__ __launch_bounds__(Cfg::NTHR *Cfg::IPB) void gemm_packed_kernel(GemmAr
     // one panel at k offset kb read from LDS buffer CUR (a constant, so the
     // LDS addresses are immediate offsets); it stages panel kb + BK into the
     // other buffer (DB == 2) or, after a barrier, into the same one
-    auto panel = [&](int kb, auto curc) __attribute__((always_inline)) {
+    auto panel = [&](int kb, auto curc, auto fullc) __attribute__((always_inline)) {
         constexpr int CUR = decltype(curc)::value;
+        constexpr bool KF = decltype(fullc)::value;
         const double *S = &smem[grp][CUR][0];
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 16) {
@@ -388,8 +390,8 @@ __global__ __launch_bounds__(Cfg::NTHR *Cfg::IPB) void gemm_packed_kernel(GemmAr
             f.read(S, kk, wm, wn, lr, lg);
             __builtin_amdgcn_s_setprio(1);
             if (kk == 0) {
-                sa.template load<BUF>(A, lda, m, k, i0, kb + BK, tid);
-                sb.template load<BUF>(B, ldb, n, k, j0, kb + BK, tid);
+                sa.template load<BUF, KF>(A, lda, m, k, i0, kb + BK, tid);
+                sb.template load<BUF, KF>(B, ldb, n, k, j0, kb + BK, tid);
                 f.mma(acc);
                 interleave_loads<4 * TM * TN, SA::LOADS + SB::LOADS>();
             } else {
@@ -406,21 +408,59 @@ __global__ __launch_bounds__(Cfg::NTHR *Cfg::IPB) void gemm_packed_kernel(GemmAr
     };
     using B0 = std::integral_constant<int, 0>;
     using B1 = std::integral_constant<int, 1>;
+    using KPart = std::false_type;
+    // panels 0 .. P - 1 run here; panel p stages panel p + 1, which lies wholly
+    // inside k unless it is the last one (p = P - 1): with KPEEL the loads of an
+    // operand stored along k ('T' A, 'N' B) skip the k test (the last one keeps
+    // it; the other operand is bounded by its record count anyway).  Register counts keep it to the
+    // workgroup tiles with 16-byte buffer loads and either one buffer of
+    // 16-deep panels or at most four MFMA tiles per wave: elsewhere the extra
+    // copy of the panel cost a wave per SIMD.
+    constexpr bool KPEEL = (TA || !TB) && !WAVE_ONLY && BUF && VEC == 2 &&
+                           ((DB == 1 && BK == 16) || TM * TN <= 4);
+    using KF = std::integral_constant<bool, KPEEL>;
+    const int P = klast / BK;
     int cur = 0;
-    if constexpr (DB == 2) {
+    if constexpr (KPEEL) {
+        if constexpr (DB == 2) {
+            if (P > 0) {
+                // two panels per trip: buffers 0 then 1
+                int p = 0;
+                for (; p + 2 < P; p += 2) {
+                    panel(p * BK, B0{}, KF{});
+                    panel((p + 1) * BK, B1{}, KF{});
+                }
+                if (p + 1 < P) {
+                    panel(p * BK, B0{}, KF{});
+                    ++p;
+                }
+                if (p & 1)
+                    panel(p * BK, B1{}, KPart{});
+                else
+                    panel(p * BK, B0{}, KPart{});
+                cur = P & 1;
+            }
+        } else {
+            int p = 0;
+            for (; p + 1 < P; ++p)
+                panel(p * BK, B0{}, KF{});
+            if (P > 0)
+                panel(p * BK, B0{}, KPart{});
+        }
+    } else if constexpr (DB == 2) {
         // two panels per trip: buffers 0 then 1
         int kb = 0;
         for (; kb + BK < klast; kb += 2 * BK) {
-            panel(kb, B0{});
-            panel(kb + BK, B1{});
+            panel(kb, B0{}, KPart{});
+            panel(kb + BK, B1{}, KPart{});
         }
         if (kb < klast) {
-            panel(kb, B0{});
+            panel(kb, B0{}, KPart{});
             cur = 1;
         }
     } else {
         for (int kb = 0; kb < klast; kb += BK)
-            panel(kb, B0{});
+            panel(kb, B0{}, KPart{});
     }
 
     // C is needed only by the epilogue: its loads overlap the last panel.
