@@ -71,6 +71,7 @@ __global__ __launch_bounds__(IPB * 64) __attribute__((amdgpu_waves_per_eu(NT <= 
 }
 
 // ---- orders up to 32: four instances per wave, whole rows in lanes ----------
+// (the order 32 itself runs the register kernel unless an instance spans 4 GiB)
 // For small orders what costs is the chain of N elimination steps, not
 // arithmetic.  Lane (g, i) of a wave holds rows i and, from order 17, i + 16
 // of instance 4w + g whole (entries right of the diagonal read from the lower
@@ -225,6 +226,11 @@ static hipError_t launch_potrf_t(const PotrfArgs &a, hipStream_t s)
 
 hipError_t launch_potrf_lower(const PotrfArgs &a, hipStream_t s)
 {
+    // at the order 32 the two full tiles in registers beat the rows kernel
+    // (17.4 against 18.8 us for 4096 instances); at 17..31 and at 16 the rows
+    // kernel is faster
+    if (a.n == 32 && (uint64_t)a.lda * (uint64_t)a.n * 8u < (1ull << 32))
+        return launch_potrf_regs<2, 4>(a, s);
     if (a.n <= POTRF_ROWS_MAX_N)
         return launch_potrf_rows_n(a.n, a, s, std::make_integer_sequence<int, POTRF_ROWS_MAX_N>{});
     const int nt = (a.n + 15) / 16;
@@ -274,6 +280,8 @@ const char *potrf_kernel_name(int n)
         "potrf_nt6", "potrf_nt7", "potrf_nt8", "potrf_nt9", "potrf_nt10", "potrf_nt11",
         "potrf_nt12", "potrf_nt13", "potrf_nt14", "potrf_nt15", "potrf_nt16", "potrf_nt17",
         "potrf_nt18", "potrf_nt19"};
+    if (n == 32)
+        return "potrf_nt2";  // the register kernel (the rows kernel below it)
     const int nt = (n + 15) / 16;
     return (nt >= 0 && nt <= 19) ? names[nt] : "unsupported";
 }
